@@ -1,0 +1,457 @@
+/*
+ * oracle.c -- plain CPU oracle for the parallel reduction (TEST INFRASTRUCTURE).
+ *
+ * What it computes (Jradi, do Nascimento, Martins, arXiv 1710.07358):
+ *   Section 1.1 defines the reduction of X = {x0..x(n-1)} as x0 (+) ... (+) x(n-1)
+ *   for an associative combiner (+, x, and, or, xor, min, max, ...), and
+ *   Algorithm 1 (Summation) states it as a left fold from the neutral element.
+ *   The footnotes of Section 1.1 note that floating-point + is not associative
+ *   (1.5 + 4^50 - 4^50 may give 0 or 1.5) and point to compensation or double
+ *   precision as remedies.
+ *
+ * How it computes it (slow on purpose, obviously correct):
+ *   - integer ops and bitwise ops: the left fold of Algorithm 1, verbatim;
+ *   - float min/max: a left fold with IEEE 754-2019 minimum/maximum semantics;
+ *   - float sum: the exact real sum of the stored values, held in a fixed-point
+ *     long accumulator (units of 2^-1074), rounded once to double;
+ *   - float product: a left fold in double-double arithmetic;
+ *   - row-wise gradients: their definitions, with exclusive prefix/suffix
+ *     products in double-double.
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this file.  It shares nothing with the GPU path.
+ *
+ * Build: gcc -O2 -fPIC -shared (no -ffast-math: the float code relies on
+ * strict IEEE evaluation and on fma being exact-then-rounded).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { DT_I32 = 0, DT_U32 = 1, DT_F32 = 2, DT_F64 = 3, DT_F16 = 4, DT_BF16 = 5 };
+enum { OP_SUM = 0, OP_PROD = 1, OP_MIN = 2, OP_MAX = 3, OP_AND = 4, OP_OR = 5, OP_XOR = 6 };
+
+/* ------------------------------------------------------------------ */
+/* Integer and bitwise folds (Algorithm 1 with the combiner swapped).   */
+/* ------------------------------------------------------------------ */
+
+int orc_fold_u32(const uint32_t* x, int64_t n, int op, int is_signed, uint32_t* out) {
+    uint32_t acc;
+    switch (op) { /* neutral elements */
+    case OP_SUM: acc = 0u; break;
+    case OP_PROD: acc = 1u; break;
+    case OP_MIN: acc = is_signed ? (uint32_t)INT32_MAX : UINT32_MAX; break;
+    case OP_MAX: acc = is_signed ? (uint32_t)INT32_MIN : 0u; break;
+    case OP_AND: acc = UINT32_MAX; break;
+    case OP_OR: acc = 0u; break;
+    case OP_XOR: acc = 0u; break;
+    default: return -1;
+    }
+    if (n < 0) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t v = x[i];
+        switch (op) {
+        case OP_SUM: acc = acc + v; break; /* unsigned: wraps mod 2^32 */
+        case OP_PROD: acc = acc * v; break;
+        case OP_MIN:
+            if (is_signed) acc = ((int32_t)v < (int32_t)acc) ? v : acc;
+            else acc = (v < acc) ? v : acc;
+            break;
+        case OP_MAX:
+            if (is_signed) acc = ((int32_t)v > (int32_t)acc) ? v : acc;
+            else acc = (v > acc) ? v : acc;
+            break;
+        case OP_AND: acc = acc & v; break;
+        case OP_OR: acc = acc | v; break;
+        case OP_XOR: acc = acc ^ v; break;
+        }
+    }
+    *out = acc;
+    return 0;
+}
+
+int orc_fold_u64(const uint64_t* x, int64_t n, int op, uint64_t* out) {
+    uint64_t acc;
+    if (op == OP_AND) acc = UINT64_MAX;
+    else if (op == OP_OR || op == OP_XOR) acc = 0u;
+    else return -1;
+    if (n < 0) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        if (op == OP_AND) acc &= x[i];
+        else if (op == OP_OR) acc |= x[i];
+        else acc ^= x[i];
+    }
+    *out = acc;
+    return 0;
+}
+
+int orc_fold_u16(const uint16_t* x, int64_t n, int op, uint16_t* out) {
+    uint16_t acc;
+    if (op == OP_AND) acc = 0xFFFFu;
+    else if (op == OP_OR || op == OP_XOR) acc = 0u;
+    else return -1;
+    if (n < 0) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        if (op == OP_AND) acc = (uint16_t)(acc & x[i]);
+        else if (op == OP_OR) acc = (uint16_t)(acc | x[i]);
+        else acc = (uint16_t)(acc ^ x[i]);
+    }
+    *out = acc;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Decoding stored float values to double (exact for every dtype).     */
+/* ------------------------------------------------------------------ */
+
+/* IEEE binary16: 1 sign, 5 exponent (bias 15), 10 fraction bits. */
+static double decode_f16(uint16_t h) {
+    int sign = (h >> 15) & 1;
+    int e = (h >> 10) & 0x1F;
+    int m = h & 0x3FF;
+    double v;
+    if (e == 0) v = ldexp((double)m, -24);                 /* subnormal: m * 2^-24 */
+    else if (e == 31) v = (m == 0) ? INFINITY : NAN;
+    else v = ldexp((double)(m | 0x400), e - 25);           /* 1.m * 2^(e-15) */
+    return sign ? -v : v;
+}
+
+/* bfloat16 is the upper half of an IEEE binary32. */
+static double decode_bf16(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
+
+double orc_load_float(const void* x, int64_t i, int dtype) {
+    switch (dtype) {
+    case DT_F32: return (double)((const float*)x)[i];
+    case DT_F64: return ((const double*)x)[i];
+    case DT_F16: return decode_f16(((const uint16_t*)x)[i]);
+    case DT_BF16: return decode_bf16(((const uint16_t*)x)[i]);
+    case DT_I32: return (double)((const int32_t*)x)[i];
+    case DT_U32: return (double)((const uint32_t*)x)[i];
+    }
+    return NAN;
+}
+
+static int is_float_dtype(int dt) { return dt == DT_F32 || dt == DT_F64 || dt == DT_F16 || dt == DT_BF16; }
+
+/* ------------------------------------------------------------------ */
+/* Exact summation: fixed-point long accumulator.                       */
+/*                                                                      */
+/* Every finite double is an integer multiple of 2^-1074 and smaller   */
+/* than 2^1024, so the sum of up to 2^40 of them is an integer times    */
+/* 2^-1074 of at most 1074+1024+40 bits.  The accumulator keeps that   */
+/* integer in base-2^32 digits, each stored in an int64 so that carries */
+/* can be propagated lazily.                                            */
+/* ------------------------------------------------------------------ */
+
+#define LA_DIGITS 72 /* 72 * 32 = 2304 bits > 2138 */
+
+typedef struct {
+    int64_t d[LA_DIGITS];
+    int64_t pending; /* additions since the last carry propagation */
+} longacc;
+
+static void la_init(longacc* a) { memset(a, 0, sizeof *a); }
+
+/* Propagate carries so every digit but the top one lies in [0, 2^32). */
+static void la_normalize(longacc* a) {
+    for (int i = 0; i < LA_DIGITS - 1; ++i) {
+        int64_t carry = a->d[i] >> 32; /* arithmetic shift: floor division */
+        a->d[i] -= carry * ((int64_t)1 << 32);
+        a->d[i + 1] += carry;
+    }
+    a->pending = 0;
+}
+
+/* Add (negate ? -1 : +1) * mant * 2^(pos - 1074), with mant < 2^53, pos >= 0. */
+static void la_add(longacc* a, uint64_t mant, int pos, int negate) {
+    int digit = pos >> 5, shift = pos & 31;
+    /* mant << shift spans at most 85 bits: split into three 32-bit pieces */
+    uint64_t lo = (mant << shift) & 0xFFFFFFFFu;
+    uint64_t mid = shift ? (mant >> (32 - shift)) & 0xFFFFFFFFu : (mant >> 32) & 0xFFFFFFFFu;
+    uint64_t hi = shift ? (mant >> (64 - shift)) : 0u;
+    if (negate) {
+        a->d[digit] -= (int64_t)lo;
+        a->d[digit + 1] -= (int64_t)mid;
+        a->d[digit + 2] -= (int64_t)hi;
+    } else {
+        a->d[digit] += (int64_t)lo;
+        a->d[digit + 1] += (int64_t)mid;
+        a->d[digit + 2] += (int64_t)hi;
+    }
+    if (++a->pending >= ((int64_t)1 << 29)) la_normalize(a);
+}
+
+/* Add the finite double v exactly. */
+static void la_add_double(longacc* a, double v, int force_positive) {
+    if (v == 0.0) return;
+    int negate = (v < 0.0) && !force_positive;
+    double m = fabs(v);
+    int e;
+    double f = frexp(m, &e);             /* m = f * 2^e, f in [0.5, 1) */
+    /* m = mant * 2^(e-53) with mant a 53-bit integer; shift so the exponent
+       is at least -1074 (subnormals have fewer significant bits). */
+    int exp2 = e - 53;
+    uint64_t mant = (uint64_t)ldexp(f, 53); /* exact: f has <= 53 significant bits */
+    if (exp2 < -1074) {
+        int drop = -1074 - exp2;         /* these low bits are zero for a valid double */
+        mant >>= drop;
+        exp2 = -1074;
+    }
+    la_add(a, mant, exp2 + 1074, negate);
+}
+
+static int la_bit(const uint32_t* mag, int k) { return (int)((mag[k >> 5] >> (k & 31)) & 1u); }
+
+/* Round the accumulated integer times 2^-1074 to the nearest double, ties to even. */
+static double la_round(longacc* a) {
+    la_normalize(a);
+    uint32_t mag[LA_DIGITS];
+    int negative = a->d[LA_DIGITS - 1] < 0;
+    /* two's complement magnitude across digits */
+    if (negative) {
+        uint64_t borrow = 1; /* -v = ~v + 1 */
+        for (int i = 0; i < LA_DIGITS; ++i) {
+            uint64_t inv = (~(uint64_t)(uint32_t)a->d[i]) & 0xFFFFFFFFu;
+            uint64_t s = inv + borrow;
+            mag[i] = (uint32_t)s;
+            borrow = s >> 32;
+        }
+    } else {
+        for (int i = 0; i < LA_DIGITS; ++i) mag[i] = (uint32_t)a->d[i];
+    }
+    int top = -1;
+    for (int k = LA_DIGITS * 32 - 1; k >= 0; --k)
+        if (la_bit(mag, k)) { top = k; break; }
+    if (top < 0) return 0.0;
+    double r;
+    if (top < 53) {
+        uint64_t m = 0;
+        for (int k = top; k >= 0; --k) m = (m << 1) | (uint64_t)la_bit(mag, k);
+        r = ldexp((double)m, -1074); /* exact */
+    } else {
+        uint64_t t = 0;
+        for (int k = top; k >= top - 52; --k) t = (t << 1) | (uint64_t)la_bit(mag, k);
+        int round_bit = la_bit(mag, top - 53);
+        int sticky = 0;
+        for (int k = top - 54; k >= 0 && !sticky; --k) sticky = la_bit(mag, k);
+        if (round_bit && (sticky || (t & 1u))) ++t;
+        int e = top - 52 - 1074;
+        if (t == ((uint64_t)1 << 53)) { t >>= 1; ++e; }
+        r = ldexp((double)t, e); /* overflows to inf exactly when it should */
+    }
+    return negative ? -r : r;
+}
+
+int orc_exact_sum(const void* x, int64_t n, int dtype, double* sum, double* abs_sum) {
+    if (!is_float_dtype(dtype) || n < 0) return -1;
+    static longacc acc, aacc; /* large; kept off the stack (oracle is single-threaded) */
+    la_init(&acc);
+    la_init(&aacc);
+    int has_nan = 0, has_pinf = 0, has_ninf = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = orc_load_float(x, i, dtype);
+        if (isnan(v)) { has_nan = 1; continue; }
+        if (isinf(v)) { if (v > 0) has_pinf = 1; else has_ninf = 1; continue; }
+        la_add_double(&acc, v, 0);
+        la_add_double(&aacc, v, 1);
+    }
+    double s = la_round(&acc);
+    double as = la_round(&aacc);
+    if (has_nan || (has_pinf && has_ninf)) s = NAN;
+    else if (has_pinf) s = INFINITY;
+    else if (has_ninf) s = -INFINITY;
+    if (has_nan) as = NAN;
+    else if (has_pinf || has_ninf) as = INFINITY;
+    if (sum) *sum = s;
+    if (abs_sum) *abs_sum = as;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Double-double product fold.                                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double hi, lo; } dd;
+
+/* (hi + lo) * b with the exact product hi*b recovered by fma. */
+static dd dd_mul_double(dd a, double b) {
+    double p = a.hi * b;
+    double e = fma(a.hi, b, -p); /* exact rounding error of a.hi*b */
+    e = fma(a.lo, b, e);
+    double s = p + e;
+    double t = e - (s - p);
+    dd r = { s, t };
+    return r;
+}
+
+static dd dd_mul(dd a, dd b) {
+    double p = a.hi * b.hi;
+    double e = fma(a.hi, b.hi, -p);
+    e += a.hi * b.lo + a.lo * b.hi;
+    double s = p + e;
+    double t = e - (s - p);
+    dd r = { s, t };
+    return r;
+}
+
+int orc_prod(const void* x, int64_t n, int dtype, double* out) {
+    if (!is_float_dtype(dtype) || n < 0) return -1;
+    dd acc = { 1.0, 0.0 };
+    for (int64_t i = 0; i < n; ++i) acc = dd_mul_double(acc, orc_load_float(x, i, dtype));
+    *out = acc.hi + acc.lo;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* IEEE 754-2019 minimum / maximum fold.                                */
+/* ------------------------------------------------------------------ */
+
+/* 1 when v should replace the current extreme cur (strictly better). */
+static int strictly_better(double v, double cur, int is_max) {
+    if (is_max) {
+        if (v > cur) return 1;
+        if (v == cur && v == 0.0 && signbit(cur) && !signbit(v)) return 1; /* +0 beats -0 */
+    } else {
+        if (v < cur) return 1;
+        if (v == cur && v == 0.0 && !signbit(cur) && signbit(v)) return 1; /* -0 beats +0 */
+    }
+    return 0;
+}
+
+int orc_minmax(const void* x, int64_t n, int dtype, int is_max, double* out, int64_t* first) {
+    if (!is_float_dtype(dtype) || n < 0) return -1;
+    double acc = is_max ? -INFINITY : INFINITY;
+    int64_t at = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = orc_load_float(x, i, dtype);
+        if (at >= 0 && isnan(acc)) break; /* NaN is absorbing; keep the first one */
+        if (isnan(v) || at < 0 || strictly_better(v, acc, is_max)) {
+            acc = v;
+            at = i;
+        }
+    }
+    *out = acc;
+    if (first) *first = at;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Segmented form.                                                      */
+/* ------------------------------------------------------------------ */
+
+int orc_segmented(const void* x, const int64_t* offsets, int64_t nseg, int dtype, int op,
+                  void* out) {
+    if (nseg < 0) return -2;
+    size_t esz = (dtype == DT_F64) ? 8 : (dtype == DT_F16 || dtype == DT_BF16) ? 2 : 4;
+    int bitwise = (op == OP_AND || op == OP_OR || op == OP_XOR);
+    for (int64_t s = 0; s < nseg; ++s) {
+        int64_t b = offsets[s], e = offsets[s + 1];
+        if (e < b) return -3;
+        const void* p = (const char*)x + (size_t)b * esz;
+        int64_t len = e - b;
+        int rc;
+        if (dtype == DT_I32 || dtype == DT_U32 || (bitwise && dtype == DT_F32)) {
+            uint32_t r;
+            rc = orc_fold_u32((const uint32_t*)p, len, op, dtype == DT_I32, &r);
+            ((uint64_t*)out)[s] = r;
+        } else if (bitwise && dtype == DT_F64) {
+            uint64_t r;
+            rc = orc_fold_u64((const uint64_t*)p, len, op, &r);
+            ((uint64_t*)out)[s] = r;
+        } else if (bitwise) {
+            uint16_t r;
+            rc = orc_fold_u16((const uint16_t*)p, len, op, &r);
+            ((uint64_t*)out)[s] = r;
+        } else if (op == OP_SUM) {
+            rc = orc_exact_sum(p, len, dtype, &((double*)out)[s], 0);
+        } else if (op == OP_PROD) {
+            rc = orc_prod(p, len, dtype, &((double*)out)[s]);
+        } else {
+            rc = orc_minmax(p, len, dtype, op == OP_MAX, &((double*)out)[s], 0);
+        }
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Row-wise forward and gradient.                                       */
+/* ------------------------------------------------------------------ */
+
+int orc_row_forward(const float* x, int64_t rows, int64_t cols, int op, double* y,
+                    int64_t* idx, int64_t* zeros) {
+    if (rows < 0 || cols < 0) return -2;
+    for (int64_t r = 0; r < rows; ++r) {
+        const float* row = x + r * cols;
+        int rc = 0;
+        if (idx) idx[r] = -1;
+        if (zeros) zeros[r] = 0;
+        if (op == OP_SUM) rc = orc_exact_sum(row, cols, DT_F32, &y[r], 0);
+        else if (op == OP_PROD) {
+            rc = orc_prod(row, cols, DT_F32, &y[r]);
+            if (zeros) {
+                int64_t z = 0;
+                for (int64_t j = 0; j < cols; ++j) z += (row[j] == 0.0f);
+                zeros[r] = z;
+            }
+        } else if (op == OP_MIN || op == OP_MAX) {
+            int64_t at;
+            rc = orc_minmax(row, cols, DT_F32, op == OP_MAX, &y[r], &at);
+            if (idx) idx[r] = at;
+        } else return -1;
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int orc_row_grad(const float* x, int64_t rows, int64_t cols, int op, const double* g,
+                 double* grad) {
+    if (rows < 0 || cols < 0) return -2;
+    for (int64_t r = 0; r < rows; ++r) {
+        const float* row = x + r * cols;
+        double* gr = grad + r * cols;
+        if (op == OP_SUM) {
+            /* d/dx_j of sum_i x_i is 1 for every j */
+            for (int64_t j = 0; j < cols; ++j) gr[j] = g[r];
+        } else if (op == OP_MIN || op == OP_MAX) {
+            /* the extreme is x at the lowest attaining index; only that entry moves it */
+            double v;
+            int64_t at;
+            int rc = orc_minmax(row, cols, DT_F32, op == OP_MAX, &v, &at);
+            if (rc) return rc;
+            for (int64_t j = 0; j < cols; ++j) gr[j] = (j == at) ? g[r] : 0.0;
+        } else if (op == OP_PROD) {
+            /* d/dx_j prod_i x_i = prod_{i<j} x_i * prod_{i>j} x_i: suffix products
+               right to left into a scratch row, then a left-to-right walk that
+               carries the prefix product. */
+            static dd* suffix = 0;
+            static int64_t cap = 0;
+            if (cap < cols + 1) {
+                dd* grown = (dd*)realloc(suffix, sizeof(dd) * (size_t)(cols + 1));
+                if (!grown) return -4;
+                suffix = grown;
+                cap = cols + 1;
+            }
+            dd run = { 1.0, 0.0 };
+            suffix[cols] = run;
+            for (int64_t j = cols - 1; j >= 0; --j) {
+                run = dd_mul_double(run, (double)row[j]);
+                suffix[j] = run; /* product of x[j..cols) */
+            }
+            dd prefix = { 1.0, 0.0 }; /* product of x[0..j) */
+            for (int64_t j = 0; j < cols; ++j) {
+                dd t = dd_mul_double(dd_mul(prefix, suffix[j + 1]), g[r]);
+                gr[j] = t.hi + t.lo;
+                prefix = dd_mul_double(prefix, (double)row[j]);
+            }
+        } else return -1;
+    }
+    return 0;
+}
