@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X parallel reduction (one JSON line on stdout).
+
+Headline: float32 sum over n = 2^28 elements (1 GiB, uniform(-1, 1), seeded),
+one launch of the plain kernel per step, inputs resident in HBM.  Bandwidth
+counts the input bytes once, in decimal GB/s -- the convention of the
+execution-time table of Section 4 (5,533,214 x 4 B / 0.249780 ms = 88.6 GB/s).
+
+Also measured (outside the timed headline loop) and reported in the same line:
+* segmented: 65,536 log-normal segments (~2^28 float32) for + and max, one
+  persistent launch per step, captured in a HIP graph and replayed; its time
+  per algorithmic byte relative to the plain kernel's;
+* row-wise forward + backward over a 4096 x 262144 float32 matrix for +, max
+  and x, time per algorithmic byte relative to the plain kernel's;
+* the compensated sum at 2^28;
+* cpu_baseline: the CPU oracle (exact long-accumulator sum, one thread) on
+  the same 2^28 input.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-secondary] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "GB/s & % of HBM peak, fp32 sum n=2^28; batched/fwd+bwd vs plain at tol"
+
+
+def gbps(nbytes: float, seconds: float) -> float:
+    """Decimal GB/s of nbytes moved in seconds."""
+    return nbytes / seconds / 1e9
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_launches(fn, steps: int, warmup: int, torch) -> float:
+    """Average seconds per call of fn() measured with HIP events on the
+    current stream (the stream every launch goes to)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3 / steps
+
+
+def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
+    lens = W.segment_lengths()
+    off = W.offsets_from_lengths(lens)
+    n = int(off[-1])
+    nseg = len(lens)
+    dev = torch.device("cuda")
+    res = {"segments": nseg, "elements": n, "lengths": "lognormal median 1024 sigma 1.6651 clip [1, 2^22]"}
+    algo_bytes = 4 * n + 8 * (nseg + 1) + 4 * nseg
+    offs = torch.from_numpy(off).to(dev)
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([rng.integers(0, nseg, 200), [int(np.argmax(lens))]]))
+    for op in ("sum", "max"):
+        x_np = W.segmented_values(n, op)
+        x = torch.from_numpy(x_np).to(dev)
+        out = torch.empty(nseg, dtype=torch.float32, device=dev)
+        ws = rd.Workspace()
+        rd.segmented(x, offs, op, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        eager = time_launches(lambda: rd.segmented(x, offs, op, out=out, workspace=ws), steps, warmup, torch)
+        # captured once, replayed
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                rd.segmented(x, offs, op, out=out, workspace=ws)
+        torch.cuda.current_stream().wait_stream(s)
+        replay = time_launches(graph.replay, steps, warmup, torch)
+        got = out.cpu().numpy().astype(np.float64)
+        worst = 0.0
+        for sidx in sample:
+            a, b = int(off[sidx]), int(off[sidx + 1])
+            seg = x_np[a:b]
+            if op == "sum":
+                ref, asum = oracle.exact_sum(seg)
+                err = abs(got[sidx] - ref) / max(asum, 1e-300)
+                worst = max(worst, err)
+                assert err <= 2.0 ** -20, (sidx, got[sidx], ref)
+            else:
+                assert got[sidx] == oracle.reduce(seg, "max", "float32"), sidx
+        t = min(eager, replay)
+        res[op] = {"ms": round(t * 1e3, 4), "ms_eager": round(eager * 1e3, 4), "ms_graph": round(replay * 1e3, 4),
+                   "GBps": round(gbps(algo_bytes, t), 1),
+                   "per_byte_vs_plain": round((t / algo_bytes) / plain_s_per_byte, 4),
+                   "checked_segments": int(len(sample)),
+                   "max_err_over_abs_sum": worst if op == "sum" else 0.0}
+        del graph
+        ws.close()
+    res["algorithmic_bytes"] = algo_bytes
+    return res
+
+
+def bench_rowwise(rd, torch, steps, warmup, plain_s_per_byte):
+    rows, cols = 4096, 262144
+    dev = torch.device("cuda")
+    gen = torch.Generator(device=dev)
+    res = {"shape": [rows, cols]}
+    n = rows * cols
+    for op in ("sum", "max", "prod"):
+        gen.manual_seed(171007358 + 4000 + {"sum": 0, "max": 30, "prod": 10}[op])
+        if op == "prod":
+            x = torch.rand(rows, cols, device=dev, generator=gen) * 0.02 + 0.99
+            x[torch.rand(rows, cols, device=dev, generator=gen) < 1e-4] = 0.0
+        else:
+            x = torch.randn(rows, cols, device=dev, generator=gen)
+        g = torch.randn(rows, device=dev, generator=gen)
+        y, saved = rd.rowreduce_forward(x, op)
+        torch.cuda.synchronize()
+        t_f = time_launches(lambda: rd.rowreduce_forward(x, op), steps, warmup, torch)
+        t_b = time_launches(lambda: rd.rowreduce_backward(x, g, saved, op), steps, warmup, torch)
+        fwd_bytes = 4 * n
+        if op == "prod":
+            zeros = (x == 0).sum(dim=1)
+            dense_rows = int((zeros == 0).sum().item())
+            bwd_bytes = 4 * n + 4 * dense_rows * cols  # write all; read x for zero-free rows
+        else:
+            bwd_bytes = 4 * n
+        t = t_f + t_b
+        res[op] = {"fwd_ms": round(t_f * 1e3, 4), "bwd_ms": round(t_b * 1e3, 4),
+                   "fwd_GBps": round(gbps(fwd_bytes, t_f), 1), "bwd_GBps": round(gbps(bwd_bytes, t_b), 1),
+                   "per_byte_vs_plain": round((t / (fwd_bytes + bwd_bytes)) / plain_s_per_byte, 4)}
+        del x, y, saved, g
+        torch.cuda.empty_cache()
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-secondary", action="store_true", help="headline kernel only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
+              "the reduction's multi-GPU form is not part of this library", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1710_07358_amd as rd
+    from paper_1710_07358_amd import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = 2 ** 28
+    log("generating input")
+    x_np = W.plain(n, "float32", "sum", config=1, salt=28)
+    x = torch.from_numpy(x_np).to(dev)
+    out = torch.empty((), dtype=torch.float32, device=dev)
+    cfg = rd.config_get("plain", torch.float32, "sum", n)
+    log(f"timing plain fp32 sum n=2^28 config={cfg}")
+    t = time_launches(lambda: rd.reduce(x, "sum", out=out), args.steps, args.warmup, torch)
+    nbytes = 4 * n
+    achieved = gbps(nbytes, t)
+    got = float(out.item())
+
+    import oracle  # CPU oracle: correctness check and the cpu_baseline leg
+
+    check = {}
+    cpu = None
+    if not args.no_cpu:
+        log("timing CPU oracle on the same input")
+        t0 = time.perf_counter()
+        ref, abs_sum = oracle.exact_sum(x_np)
+        t_cpu = time.perf_counter() - t0
+        err = abs(got - ref)
+        check = {"exact": ref, "gpu": got, "abs_err": err, "abs_sum": abs_sum,
+                 "err_over_abs_sum": err / abs_sum, "tol": "2^-20*sum|x|",
+                 "pass": err <= 2.0 ** -20 * abs_sum}
+        cpu = {"value": round(gbps(nbytes, t_cpu), 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload: 2^28 fp32, exact long-accumulator sum, single thread",
+               "seconds": round(t_cpu, 3)}
+
+    secondary = {}
+    if not args.no_secondary:
+        plain_spb = t / nbytes
+        log("compensated sum")
+        outc = torch.empty((), dtype=torch.float64, device=dev)
+        tc = time_launches(lambda: rd.reduce_compensated(x, out=outc), args.steps, args.warmup, torch)
+        secondary["compensated"] = {"ms": round(tc * 1e3, 4), "GBps": round(gbps(nbytes, tc), 1)}
+        if check:
+            ec = abs(float(outc.item()) - check["exact"])
+            secondary["compensated"].update({"abs_err": ec, "err_over_abs_sum": ec / check["abs_sum"],
+                                             "pass": ec <= 2.0 ** -40 * check["abs_sum"]})
+        del x
+        torch.cuda.empty_cache()
+        log("segmented")
+        secondary["segmented"] = bench_segmented(rd, W, oracle, torch, np, max(args.steps // 2, 5),
+                                                 args.warmup, plain_spb)
+        log("row-wise forward + backward")
+        secondary["rowwise"] = bench_rowwise(rd, torch, max(args.steps // 5, 3), 2, plain_spb)
+
+    line = {
+        "metric": METRIC,
+        "value": round(achieved, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain float32 sum, n=2^28 (1 GiB) uniform(-1,1), seeded PCG64",
+                   "global_batch": n, "seq_len": 1, "parallelism": "single GPU",
+                   "launch": cfg},
+        "pct_hbm_peak": round(100.0 * achieved / HBM_PEAK_GBPS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "reduce_kernel<F32 sum>", "bytes_per_launch": nbytes,
+                     "avg_launch_ms": round(t * 1e3, 5)},
+        "cpu_baseline": cpu,
+        "check": check,
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,195 @@
+/*
+ * rd.h -- C ABI of librd, an MI355X (gfx950) parallel-reduction library.
+ *
+ * The operation is the reduction of Section 1.1 ("Problem Definition") of
+ * Jradi, do Nascimento and Martins, "A Fast and Generic GPU-Based Parallel
+ * Reduction Implementation" (arXiv 1710.07358): given X = {x0, ..., x(n-1)},
+ * compute x0 (+) x1 (+) ... (+) x(n-1) for an associative combiner (+).  The
+ * combiners offered are the ones Section 1.1 lists that act on numbers:
+ * +, x, min, max, and, or, xor (set intersection/union on bitsets are
+ * and/or on the same bits).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named x, offsets, out, y, saved, g, grad_in are DEVICE pointers
+ *   owned by the caller; the library never frees them.  Element arrays must
+ *   be aligned to their element size; any further alignment is optional.
+ * - stream is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *   call only enqueues work on it: nothing synchronises, and results are
+ *   valid once the stream has reached that point.
+ * - Every call returns an rd_status; no exception or abort crosses the ABI.
+ *   Host-detected errors return before anything is enqueued.  A failed HIP
+ *   launch returns RD_ERR_HIP.  rd_last_error() then describes the failure
+ *   (thread-local, valid until the next call on the same thread).
+ * - n = 0 (or an empty segment) yields the neutral element of the op:
+ *   + -> 0, x -> 1, min -> +inf / INT32_MAX / UINT32_MAX,
+ *   max -> -inf / INT32_MIN / 0, and -> all ones, or/xor -> 0.
+ * - Integer + and x wrap modulo 2^32.  min/max on floats follow IEEE 754-2019
+ *   minimum/maximum: a NaN anywhere gives NaN, and -0 < +0.  and/or/xor on a
+ *   float dtype act on the stored bit patterns.
+ * - Float results are deterministic: the same input, size and configuration
+ *   give bitwise-identical output on every run.
+ */
+#ifndef RD_H
+#define RD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rd_dtype {
+    RD_I32 = 0,  /* int32 */
+    RD_U32 = 1,  /* uint32 */
+    RD_F32 = 2,  /* IEEE binary32 */
+    RD_F64 = 3,  /* IEEE binary64 */
+    RD_F16 = 4,  /* IEEE binary16 */
+    RD_BF16 = 5  /* bfloat16 (upper half of a binary32) */
+} rd_dtype;
+
+typedef enum rd_op {
+    RD_SUM = 0, RD_PROD = 1, RD_MIN = 2, RD_MAX = 3, RD_AND = 4, RD_OR = 5, RD_XOR = 6
+} rd_op;
+
+typedef enum rd_status {
+    RD_OK = 0,
+    RD_ERR_INVALID_ARG = -1, /* null pointer, negative size, misaligned pointer, bad enum */
+    RD_ERR_UNSUPPORTED = -2, /* (dtype, op) pair the entry point does not offer */
+    RD_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    RD_ERR_NOMEM = -4,       /* device allocation failed */
+    RD_ERR_CAPTURE = -5,     /* would allocate while the stream is being captured */
+    RD_ERR_WORKSPACE = -6    /* workspace belongs to another device or is too small */
+} rd_status;
+
+/* Opaque per-stream scratch: one partial per work-group plus a completion
+ * counter (the "vector of |SM| partial results" of Section 2.3, filled and
+ * consumed inside one launch).  One workspace must not be used by two calls
+ * that may run concurrently.  Passing ws = NULL uses a default workspace
+ * owned by the library, one per (device, stream), created on first use. */
+typedef struct rd_workspace rd_workspace;
+
+/* Launch configuration (Section 3: unroll factor F; Section 2.5: persistent
+ * grid of only as many work-groups as run concurrently). */
+typedef struct rd_config {
+    int block;          /* work-items per work-group: 64..1024, multiple of 64 */
+    int unroll;         /* independent 16-byte loads per work-item per step: 1, 2, 4, 8, 16 */
+    int blocks_per_cu;  /* persistent grid = blocks_per_cu x compute units (capped by the work) */
+    int nontemporal;    /* 1: stream the input with non-temporal loads */
+} rd_config;
+
+/* Kinds of launch a configuration applies to. */
+typedef enum rd_kind { RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2 } rd_kind;
+
+/* ---- library and workspace management ---------------------------------- */
+
+/* Query the current device (compute-unit count, architecture).  Called
+ * implicitly by every entry point; returns RD_ERR_HIP without a device. */
+rd_status rd_init(void);
+
+/* Create a workspace on the given device (allocates device memory; must not
+ * be called while a stream of that device is being captured). */
+rd_status rd_workspace_create(rd_workspace** ws, int device);
+rd_status rd_workspace_destroy(rd_workspace* ws);
+/* Re-zero the workspace's completion counter on stream (only needed after a
+ * launch that failed part-way). */
+rd_status rd_workspace_reset(rd_workspace* ws, void* stream);
+
+/* Element size in bytes of a dtype (0 for an invalid value). */
+size_t rd_dtype_size(rd_dtype dt);
+
+/* Output dtype of rd_reduce / rd_segmented_reduce for (dt, op): integers and
+ * float32/float64 keep their dtype; float16/bfloat16 give float32 for + and x
+ * (accumulated in float32) and keep their dtype for min/max/and/or/xor. */
+rd_status rd_out_dtype(rd_dtype dt, rd_op op, rd_dtype* out);
+
+/* ---- plain reduction ------------------------------------------------------ */
+
+/* out[0] = x[0] (+) ... (+) x[n-1]  (Section 1.1; Algorithm 1 for +).
+ *   x   : device array of n elements of dtype dt (element-aligned)
+ *   n   : number of elements, n >= 0
+ *   out : device pointer to ONE element of rd_out_dtype(dt, op)
+ *   ws  : workspace or NULL
+ * One kernel launch: each work-item folds 16-byte loads of a persistent
+ * grid-stride loop into private accumulators, each wavefront combines its
+ * lanes with cross-lane (DPP) operations, each work-group combines its
+ * wavefronts through LDS, and the last work-group to finish folds the
+ * per-work-group partials in index order and writes out. */
+rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
+                    rd_workspace* ws, void* stream);
+
+/* Compensated sum (the Kahan-style remedy the footnotes of Section 1.1
+ * mention): every work-item keeps error-free two-sum (value, error) pairs in
+ * float32, and the pairs are merged in float64 double-double arithmetic.
+ *   dt  : RD_F32, RD_F16 or RD_BF16 (else RD_ERR_UNSUPPORTED)
+ *   out : device pointer to ONE double */
+rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out,
+                                rd_workspace* ws, void* stream);
+
+/* ---- segmented reduction ------------------------------------------------- */
+
+/* out[s] = x[offsets[s]] (+) ... (+) x[offsets[s+1]-1] for s in [0, nseg),
+ * all segments in ONE persistent launch (capturable in a HIP graph).
+ *   offsets : device int64 array of nseg+1 non-decreasing entries; only
+ *             x[offsets[0] .. offsets[nseg]) is read
+ *   out     : device array of nseg elements of rd_out_dtype(dt, op)
+ * Work is split into equal element ranges, one per wavefront; segments that
+ * straddle ranges are finished by the last work-group, folding the pieces in
+ * range order (deterministic).  Offsets that decrease give unspecified values
+ * for the affected segments but never reads outside
+ * [offsets[0], offsets[nseg]). */
+rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nseg, rd_dtype dt,
+                              rd_op op, void* out, rd_workspace* ws, void* stream);
+
+/* ---- row-wise reduction and its gradient --------------------------------- */
+
+/* Bytes of the `saved` buffer rd_rowreduce_fwd fills for rd_rowreduce_bwd:
+ * 0 for sum, 8*rows (lowest extreme index) for min/max, and per-row zero
+ * bookkeeping plus per-chunk products for product. */
+size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols);
+
+/* y[r] = x[r,0] (+) ... (+) x[r,cols-1] for a row-major float32 matrix.
+ *   dt    : RD_F32;  op : RD_SUM, RD_MAX, RD_MIN or RD_PROD
+ *   y     : device float32[rows]
+ *   saved : device buffer of rd_saved_bytes(op, rows, cols) bytes (may be
+ *           NULL for RD_SUM); min/max store the LOWEST column attaining the
+ *           extreme; product stores the zero count, the first zero's column,
+ *           the product of the nonzero entries and per-chunk products. */
+rd_status rd_rowreduce_fwd(const void* x, int64_t rows, int64_t cols, rd_dtype dt, rd_op op,
+                           void* y, void* saved, void* stream);
+
+/* grad_in[r,j] = d y[r] / d x[r,j] * g[r]:
+ *   sum     -> g[r] everywhere;
+ *   min/max -> g[r] at the saved lowest extreme index, 0 elsewhere;
+ *   product -> g[r] * prod_{i != j} x[r,i], formed from prefix and suffix
+ *              products (no division); rows with one zero get g*prod(nonzeros)
+ *              at the zero and 0 elsewhere; rows with two or more zeros get 0.
+ *   x       : the forward input (read only for product rows without zeros)
+ *   g       : device float32[rows];  saved : as filled by rd_rowreduce_fwd
+ *   grad_in : device float32[rows, cols] */
+rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int64_t rows,
+                           int64_t cols, rd_dtype dt, rd_op op, void* grad_in, void* stream);
+
+/* ---- configuration and tuning --------------------------------------------- */
+
+/* Configuration the library would use for (kind, dt, op, n). */
+rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_config* cfg);
+
+/* Force one configuration for every later launch of `kind` (NULL clears it).
+ * Used by the autotuner and by tests that sweep configurations. */
+rd_status rd_config_force(rd_kind kind, const rd_config* cfg);
+
+/* Load a tuned table written by the autotuner (NULL restores the built-in
+ * defaults).  Format: one line per entry,
+ *   kind dtype_size op_class log2n_lo log2n_hi block unroll blocks_per_cu nontemporal
+ * with op_class 0 = sum/prod, 1 = min/max, 2 = and/or/xor; '#' starts a comment. */
+rd_status rd_tune_load(const char* path);
+
+/* Description of the last non-OK status returned on this thread. */
+const char* rd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,19 @@
+// k_f64_plain.hip -- instantiations of the plain and compensated kernels: float64 and 64-bit bit patterns.
+#include "reduce_plain.hpp"
+
+namespace rd {
+
+PlainFn plain_f64(rd_op op, int u, bool nt) {
+  switch (op) {
+    case RD_SUM: return pick<Red<Store::F64, Op::Sum>>(u, nt);
+    case RD_PROD: return pick<Red<Store::F64, Op::Prod>>(u, nt);
+    case RD_MIN: return pick<Red<Store::F64, Op::Min>>(u, nt);
+    case RD_MAX: return pick<Red<Store::F64, Op::Max>>(u, nt);
+    case RD_AND: return pick<Red<Store::U64, Op::And>>(u, nt);
+    case RD_OR: return pick<Red<Store::U64, Op::Or>>(u, nt);
+    case RD_XOR: return pick<Red<Store::U64, Op::Xor>>(u, nt);
+  }
+  return nullptr;
+}
+
+}  // namespace rd

@@ -1,0 +1,484 @@
+// rd_api.cpp -- the C ABI declared in include/rd.h: argument validation,
+// workspaces, launch-configuration table and dispatch to the kernels.
+//
+// Launch planning follows Section 2.5 (persistent threads): the grid holds
+// only as many work-groups as the device runs at once (blocks_per_cu x CUs),
+// capped by the amount of work, and the kernels loop over the data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "rd.h"
+#include "rd_internal.hpp"
+
+struct rd_workspace {
+  int device;
+  void* mem;
+  size_t bytes;
+  rd::Scratch scratch;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rd_status fail(rd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+rd_status hip_fail(hipError_t e, const char* what) {
+  return fail(RD_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ---- device properties -----------------------------------------------------
+
+struct DeviceInfo {
+  int cus = 0;
+  bool ok = false;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_devices;
+
+rd_status current_device(int* dev, DeviceInfo* info) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_mu);
+  DeviceInfo& d = g_devices[*dev];
+  if (!d.ok) {
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, *dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    d.cus = cus > 0 ? cus : 1;
+    d.ok = true;
+  }
+  *info = d;
+  return RD_OK;
+}
+
+// ---- workspaces ------------------------------------------------------------
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Layout: [ticket | per-wavefront counters] (zeroed region), partials, carries.
+size_t counters_bytes() { return round_up(kAlign + (size_t)rd::kMaxSegWaves * 4, kAlign); }
+
+size_t workspace_bytes() {
+  return counters_bytes() + round_up((size_t)rd::kMaxGrid * 16, kAlign) +
+         round_up((size_t)rd::kMaxSegWaves * 2 * 16, kAlign);
+}
+
+rd_status create_workspace(rd_workspace** out, int device) {
+  int prev = -1;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (device != prev && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rd_workspace* ws = new rd_workspace();
+  ws->device = device;
+  ws->bytes = workspace_bytes();
+  ws->mem = nullptr;
+  e = hipMalloc(&ws->mem, ws->bytes);
+  if (e == hipSuccess) e = hipMemset(ws->mem, 0, ws->bytes);  // counters start at zero
+  if (device != prev) (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    if (ws->mem) (void)hipFree(ws->mem);
+    delete ws;
+    return e == hipErrorOutOfMemory ? fail(RD_ERR_NOMEM, "workspace: out of device memory")
+                                    : hip_fail(e, "workspace allocation");
+  }
+  char* p = (char*)ws->mem;
+  rd::Scratch& s = ws->scratch;
+  s.ticket = (unsigned*)p;
+  s.counters = (unsigned*)(p + kAlign);
+  p += counters_bytes();
+  s.partial = p;
+  s.partial_cap = rd::kMaxGrid;
+  p += round_up((size_t)rd::kMaxGrid * 16, kAlign);
+  s.carry = p;
+  s.carry_cap = (int64_t)rd::kMaxSegWaves * 2;
+  *out = ws;
+  return RD_OK;
+}
+
+std::map<std::pair<int, hipStream_t>, rd_workspace*> g_default_ws;
+
+// Resolve the caller's workspace or the default one for (device, stream).
+rd_status resolve_workspace(rd_workspace* given, int device, hipStream_t s, rd_workspace** ws) {
+  if (given) {
+    if (given->device != device)
+      return fail(RD_ERR_WORKSPACE, "workspace belongs to device %d, current device is %d",
+                  given->device, device);
+    *ws = given;
+    return RD_OK;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto key = std::make_pair(device, s);
+  auto it = g_default_ws.find(key);
+  if (it != g_default_ws.end()) {
+    *ws = it->second;
+    return RD_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(RD_ERR_CAPTURE,
+                "the default workspace for this stream would be allocated during graph capture; "
+                "call once before capturing or pass a workspace");
+  rd_workspace* w = nullptr;
+  rd_status st = create_workspace(&w, device);
+  if (st != RD_OK) return st;
+  g_default_ws[key] = w;
+  *ws = w;
+  return RD_OK;
+}
+
+// ---- launch configuration table -------------------------------------------
+
+struct TuneEntry {
+  int kind, esize, opclass, lo, hi;  // log2(n) range [lo, hi]
+  rd_config cfg;
+};
+
+int op_class(rd_op op) {
+  if (op == RD_SUM || op == RD_PROD) return 0;
+  if (op == RD_MIN || op == RD_MAX) return 1;
+  return 2;
+}
+
+std::vector<TuneEntry> builtin_table() {
+  // Defaults before tuning: 256 work-items, U = 8 x 16-byte loads, 8 groups
+  // per CU, non-temporal streaming for inputs far beyond the 256 MB MALL.
+  std::vector<TuneEntry> t;
+  for (int kind = 0; kind < 3; ++kind)
+    for (int es : {2, 4, 8})
+      for (int oc = 0; oc < 3; ++oc) {
+        t.push_back({kind, es, oc, 0, 17, {256, 2, 8, 0}});
+        t.push_back({kind, es, oc, 18, 23, {256, 4, 8, 0}});
+        t.push_back({kind, es, oc, 24, 62, {256, 8, 8, 1}});
+      }
+  return t;
+}
+
+std::vector<TuneEntry> g_table = builtin_table();
+bool g_forced[3] = {false, false, false};
+rd_config g_force_cfg[3];
+
+int log2_ceil(int64_t n) {
+  int l = 0;
+  while (l < 62 && ((int64_t)1 << l) < n) ++l;
+  return l;
+}
+
+rd_config choose_config(rd_kind kind, rd_dtype dt, rd_op op, int64_t n) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (g_forced[kind]) return g_force_cfg[kind];
+  const int es = (int)rd_dtype_size(dt), oc = op_class(op), l = log2_ceil(n);
+  for (const TuneEntry& e : g_table)
+    if (e.kind == (int)kind && e.esize == es && e.opclass == oc && l >= e.lo && l <= e.hi) return e.cfg;
+  return rd_config{256, 8, 8, 0};
+}
+
+bool valid_config(const rd_config& c) {
+  const bool u_ok = c.unroll == 1 || c.unroll == 2 || c.unroll == 4 || c.unroll == 8 || c.unroll == 16;
+  return c.block >= 64 && c.block <= 1024 && c.block % 64 == 0 && u_ok && c.blocks_per_cu >= 1 &&
+         c.blocks_per_cu <= 64 && (c.nontemporal == 0 || c.nontemporal == 1);
+}
+
+// Persistent grid: min(work chunks, blocks_per_cu x CUs, workspace capacity).
+rd::Launch plan(const rd_config& c, int64_t nvec, int cus, int cap) {
+  const int64_t per_chunk = (int64_t)c.block * c.unroll;
+  int64_t chunks = (nvec + per_chunk - 1) / per_chunk;
+  int64_t g = std::min<int64_t>((int64_t)c.blocks_per_cu * cus, cap);
+  g = std::max<int64_t>(1, std::min(g, chunks));
+  return rd::Launch{c.block, (int)g, c.unroll, c.nontemporal != 0};
+}
+
+bool valid_dtype(rd_dtype dt) { return dt >= RD_I32 && dt <= RD_BF16; }
+bool valid_op(rd_op op) { return op >= RD_SUM && op <= RD_XOR; }
+
+rd_status check_ptr(const void* p, size_t align, const char* name) {
+  if (!p) return fail(RD_ERR_INVALID_ARG, "%s is NULL", name);
+  if ((uintptr_t)p % align) return fail(RD_ERR_INVALID_ARG, "%s is not aligned to %zu bytes", name, align);
+  return RD_OK;
+}
+
+}  // namespace
+
+namespace rd {
+
+PlainFn plain_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
+  switch (dt) {
+    case RD_I32:
+    case RD_U32: return plain_int(dt, op, unroll, nt);
+    case RD_F32: return plain_f32(op, unroll, nt);
+    case RD_F64: return plain_f64(op, unroll, nt);
+    case RD_F16:
+    case RD_BF16: return plain_half(dt, op, unroll, nt);
+  }
+  return nullptr;
+}
+
+PlainFn compensated_launcher(rd_dtype dt, int unroll, bool nt) {
+  switch (dt) {
+    case RD_F32: return comp_f32(unroll, nt);
+    case RD_F16:
+    case RD_BF16: return comp_half(dt, unroll, nt);
+    default: return nullptr;
+  }
+}
+
+SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
+  switch (dt) {
+    case RD_I32:
+    case RD_U32: return seg_int(dt, op, unroll, nt);
+    case RD_F32: return seg_f32(op, unroll, nt);
+    case RD_F64: return seg_f64(op, unroll, nt);
+    case RD_F16:
+    case RD_BF16: return seg_half(dt, op, unroll, nt);
+  }
+  return nullptr;
+}
+
+}  // namespace rd
+
+extern "C" {
+
+rd_status rd_init(void) {
+  int dev;
+  DeviceInfo info;
+  return current_device(&dev, &info);
+}
+
+size_t rd_dtype_size(rd_dtype dt) {
+  switch (dt) {
+    case RD_I32: case RD_U32: case RD_F32: return 4;
+    case RD_F64: return 8;
+    case RD_F16: case RD_BF16: return 2;
+  }
+  return 0;
+}
+
+rd_status rd_out_dtype(rd_dtype dt, rd_op op, rd_dtype* out) {
+  if (!valid_dtype(dt) || !valid_op(op) || !out) return fail(RD_ERR_INVALID_ARG, "rd_out_dtype: bad argument");
+  *out = ((dt == RD_F16 || dt == RD_BF16) && (op == RD_SUM || op == RD_PROD)) ? RD_F32 : dt;
+  return RD_OK;
+}
+
+rd_status rd_workspace_create(rd_workspace** ws, int device) {
+  if (!ws) return fail(RD_ERR_INVALID_ARG, "rd_workspace_create: ws is NULL");
+  return create_workspace(ws, device);
+}
+
+rd_status rd_workspace_destroy(rd_workspace* ws) {
+  if (!ws) return RD_OK;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto it = g_default_ws.begin(); it != g_default_ws.end(); ++it)
+      if (it->second == ws) return fail(RD_ERR_INVALID_ARG, "cannot destroy a default workspace");
+  }
+  hipError_t e = hipFree(ws->mem);
+  delete ws;
+  return e == hipSuccess ? RD_OK : hip_fail(e, "hipFree");
+}
+
+rd_status rd_workspace_reset(rd_workspace* ws, void* stream) {
+  if (!ws) return fail(RD_ERR_INVALID_ARG, "rd_workspace_reset: ws is NULL");
+  hipError_t e = hipMemsetAsync(ws->scratch.ticket, 0, counters_bytes(), (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "hipMemsetAsync");
+}
+
+rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out, rd_workspace* ws,
+                    void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "rd_reduce: invalid dtype %d", (int)dt);
+  if (!valid_op(op)) return fail(RD_ERR_INVALID_ARG, "rd_reduce: invalid op %d", (int)op);
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "rd_reduce: n = %lld < 0", (long long)n);
+  const size_t es = rd_dtype_size(dt);
+  rd_dtype odt;
+  rd_out_dtype(dt, op, &odt);
+  rd_status st;
+  if (n > 0 && (st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(out, rd_dtype_size(odt), "out")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  const rd_config cfg = choose_config(RD_KIND_PLAIN, dt, op, n);
+  rd::PlainFn fn = rd::plain_launcher(dt, op, cfg.unroll, cfg.nontemporal != 0);
+  if (!fn) return fail(RD_ERR_UNSUPPORTED, "rd_reduce: no kernel for dtype %d op %d unroll %d", (int)dt, (int)op, cfg.unroll);
+  const rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, info.cus, (int)w->scratch.partial_cap);
+  hipError_t e = fn(n > 0 ? x : out, n, out, w->scratch, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce launch");
+}
+
+rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out, rd_workspace* ws,
+                                void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "rd_reduce_compensated: invalid dtype %d", (int)dt);
+  if (dt != RD_F32 && dt != RD_F16 && dt != RD_BF16)
+    return fail(RD_ERR_UNSUPPORTED, "rd_reduce_compensated: dtype %d (float32, float16, bfloat16 only)", (int)dt);
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "rd_reduce_compensated: n < 0");
+  const size_t es = rd_dtype_size(dt);
+  rd_status st;
+  if (n > 0 && (st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(out, 8, "out")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  const rd_config cfg = choose_config(RD_KIND_COMPENSATED, dt, RD_SUM, n);
+  rd::PlainFn fn = rd::compensated_launcher(dt, cfg.unroll, cfg.nontemporal != 0);
+  if (!fn) return fail(RD_ERR_UNSUPPORTED, "rd_reduce_compensated: no kernel for unroll %d", cfg.unroll);
+  const rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, info.cus, (int)w->scratch.partial_cap);
+  hipError_t e = fn(n > 0 ? x : (const void*)out, n, out, w->scratch, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce_compensated launch");
+}
+
+rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nseg, rd_dtype dt, rd_op op,
+                              void* out, rd_workspace* ws, void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "rd_segmented_reduce: invalid dtype %d", (int)dt);
+  if (!valid_op(op)) return fail(RD_ERR_INVALID_ARG, "rd_segmented_reduce: invalid op %d", (int)op);
+  if (nseg < 0) return fail(RD_ERR_INVALID_ARG, "rd_segmented_reduce: nseg < 0");
+  if (nseg == 0) return RD_OK;
+  const size_t es = rd_dtype_size(dt);
+  rd_dtype odt;
+  rd_out_dtype(dt, op, &odt);
+  rd_status st;
+  if ((st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(offsets, 8, "offsets")) != RD_OK) return st;
+  if ((st = check_ptr(out, rd_dtype_size(odt), "out")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  const rd_config cfg = choose_config(RD_KIND_SEGMENTED, dt, op, (int64_t)1 << 28);
+  rd::SegFn fn = rd::segmented_launcher(dt, op, cfg.unroll, cfg.nontemporal != 0);
+  if (!fn) return fail(RD_ERR_UNSUPPORTED, "rd_segmented_reduce: no kernel for dtype %d op %d", (int)dt, (int)op);
+  // The element count lives on the device (offsets[nseg]); the grid is the
+  // persistent maximum and the kernel divides the range it reads.
+  const int waves_per_block = cfg.block / 64;
+  int grid = std::min(cfg.blocks_per_cu * info.cus, rd::kMaxSegWaves / waves_per_block);
+  grid = std::max(grid, 1);
+  const rd::Launch l{cfg.block, grid, cfg.unroll, cfg.nontemporal != 0};
+  hipError_t e = fn(x, offsets, nseg, out, w->scratch, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_segmented_reduce launch");
+}
+
+size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
+  if (rows < 0 || cols < 0) return 0;
+  return rd::rowreduce_saved_bytes(op, rows, cols);
+}
+
+rd_status rd_rowreduce_fwd(const void* x, int64_t rows, int64_t cols, rd_dtype dt, rd_op op, void* y,
+                           void* saved, void* stream) {
+  if (dt != RD_F32) return fail(RD_ERR_UNSUPPORTED, "rd_rowreduce_fwd: float32 only");
+  if (op != RD_SUM && op != RD_MAX && op != RD_MIN && op != RD_PROD)
+    return fail(RD_ERR_UNSUPPORTED, "rd_rowreduce_fwd: op %d (sum, max, min, prod only)", (int)op);
+  if (rows < 0 || cols < 0) return fail(RD_ERR_INVALID_ARG, "rd_rowreduce_fwd: negative shape");
+  if (cols > INT32_MAX) return fail(RD_ERR_INVALID_ARG, "rd_rowreduce_fwd: cols > 2^31 - 1");
+  if (rows == 0) return RD_OK;
+  rd_status st;
+  if (cols > 0 && (st = check_ptr(x, 4, "x")) != RD_OK) return st;
+  if ((st = check_ptr(y, 4, "y")) != RD_OK) return st;
+  if (op != RD_SUM && (st = check_ptr(saved, 8, "saved")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  hipError_t e = rd::rowreduce_fwd((const float*)x, rows, cols, op, (float*)y, saved, info.cus, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_fwd launch");
+}
+
+rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int64_t rows, int64_t cols,
+                           rd_dtype dt, rd_op op, void* grad_in, void* stream) {
+  if (dt != RD_F32) return fail(RD_ERR_UNSUPPORTED, "rd_rowreduce_bwd: float32 only");
+  if (op != RD_SUM && op != RD_MAX && op != RD_MIN && op != RD_PROD)
+    return fail(RD_ERR_UNSUPPORTED, "rd_rowreduce_bwd: op %d (sum, max, min, prod only)", (int)op);
+  if (rows < 0 || cols < 0) return fail(RD_ERR_INVALID_ARG, "rd_rowreduce_bwd: negative shape");
+  if (cols > INT32_MAX) return fail(RD_ERR_INVALID_ARG, "rd_rowreduce_bwd: cols > 2^31 - 1");
+  if (rows == 0 || cols == 0) return RD_OK;
+  rd_status st;
+  if ((st = check_ptr(g, 4, "g")) != RD_OK) return st;
+  if ((st = check_ptr(grad_in, 4, "grad_in")) != RD_OK) return st;
+  if (op != RD_SUM && (st = check_ptr(saved, 8, "saved")) != RD_OK) return st;
+  if (op == RD_PROD && (st = check_ptr(x, 4, "x")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  hipError_t e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in,
+                                   info.cus, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_bwd launch");
+}
+
+rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_config* cfg) {
+  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED || !valid_dtype(dt) || !valid_op(op))
+    return fail(RD_ERR_INVALID_ARG, "rd_config_get: bad argument");
+  *cfg = choose_config(kind, dt, op, n);
+  return RD_OK;
+}
+
+rd_status rd_config_force(rd_kind kind, const rd_config* cfg) {
+  if (kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
+  if (cfg && !valid_config(*cfg))
+    return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d",
+                cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal);
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_forced[kind] = cfg != nullptr;
+  if (cfg) g_force_cfg[kind] = *cfg;
+  return RD_OK;
+}
+
+rd_status rd_tune_load(const char* path) {
+  if (!path) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_table = builtin_table();
+    return RD_OK;
+  }
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(RD_ERR_INVALID_ARG, "rd_tune_load: cannot open %s", path);
+  std::vector<TuneEntry> t;
+  char line[512];
+  int lineno = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    char* hash = std::strchr(line, '#');
+    if (hash) *hash = 0;
+    TuneEntry e;
+    int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &e.kind, &e.esize, &e.opclass, &e.lo, &e.hi,
+                        &e.cfg.block, &e.cfg.unroll, &e.cfg.blocks_per_cu, &e.cfg.nontemporal);
+    if (k <= 0) continue;
+    if (k != 9 || e.kind < 0 || e.kind > 2 || !valid_config(e.cfg)) {
+      std::fclose(f);
+      return fail(RD_ERR_INVALID_ARG, "rd_tune_load: %s:%d: malformed entry", path, lineno);
+    }
+    t.push_back(e);
+  }
+  std::fclose(f);
+  // Entries not covered by the file keep the built-in defaults (appended last,
+  // so file entries take precedence).
+  std::vector<TuneEntry> d = builtin_table();
+  t.insert(t.end(), d.begin(), d.end());
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_table = t;
+  return RD_OK;
+}
+
+const char* rd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

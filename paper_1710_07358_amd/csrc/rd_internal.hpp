@@ -1,0 +1,69 @@
+// rd_internal.hpp -- host-side interface between the C ABI (rd_api.cpp) and
+// the kernel translation units.  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd.h"
+
+namespace rd {
+
+// Launch shape resolved by the host: work-items per group, groups, unroll U
+// (16-byte loads in flight per work-item per step), non-temporal loads.
+struct Launch {
+  int block;
+  int grid;
+  int unroll;
+  bool nontemporal;
+};
+
+// Device scratch handed to a kernel: a completion counter and room for one
+// partial per work-group (16 bytes each) and the segmented carries.
+struct Scratch {
+  unsigned* ticket;     // zero between launches; the last work-group re-zeroes it
+  unsigned* counters;   // segmented: one per wavefront, zero between launches
+  void* partial;        // >= grid * 16 bytes
+  void* carry;          // segmented: >= 2 * wavefronts * 16 bytes
+  int64_t partial_cap;  // entries of 16 bytes
+  int64_t carry_cap;    // carry entries of 16 bytes
+};
+
+// Upper bounds the workspace is sized for.
+constexpr int kMaxGrid = 8192;
+constexpr int kMaxSegWaves = 32768;
+
+using PlainFn = hipError_t (*)(const void* x, int64_t n, void* out, const Scratch& ws,
+                               const Launch& l, hipStream_t s);
+using SegFn = hipError_t (*)(const void* x, const int64_t* offsets, int64_t nseg, void* out,
+                             const Scratch& ws, const Launch& l, hipStream_t s);
+
+// nullptr when (dt, op) is not offered or the unroll has no instantiation
+// (plain/compensated: 1, 2, 4, 8, 16; segmented: 2, 4, 8).
+PlainFn plain_launcher(rd_dtype dt, rd_op op, int unroll, bool nontemporal);
+PlainFn compensated_launcher(rd_dtype dt, int unroll, bool nontemporal);
+SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nontemporal);
+
+// Per-family instantiations, one translation unit each (parallel builds).
+// *_bits32 / *_bits16 / *_bits64: and, or, xor on raw bit patterns.
+PlainFn plain_int(rd_dtype dt, rd_op op, int unroll, bool nt);  // RD_I32 / RD_U32
+PlainFn plain_bits32(rd_op op, int unroll, bool nt);
+PlainFn plain_f32(rd_op op, int unroll, bool nt);
+PlainFn plain_f64(rd_op op, int unroll, bool nt);  // includes 64-bit bitwise
+PlainFn plain_half(rd_dtype dt, rd_op op, int unroll, bool nt);  // RD_F16 / RD_BF16, 16-bit bitwise
+PlainFn comp_f32(int unroll, bool nt);
+PlainFn comp_half(rd_dtype dt, int unroll, bool nt);
+SegFn seg_int(rd_dtype dt, rd_op op, int unroll, bool nt);
+SegFn seg_bits32(rd_op op, int unroll, bool nt);
+SegFn seg_f32(rd_op op, int unroll, bool nt);
+SegFn seg_f64(rd_op op, int unroll, bool nt);
+SegFn seg_half(rd_dtype dt, rd_op op, int unroll, bool nt);
+
+// Row-wise forward / backward (float32).
+hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, float* y,
+                         void* saved, int cus, hipStream_t s);
+hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows,
+                         int64_t cols, rd_op op, float* grad, int cus, hipStream_t s);
+size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols);
+
+}  // namespace rd

@@ -1,0 +1,86 @@
+"""Shared test plumbing: moving seeded numpy inputs to the GPU and reading
+GPU results back in the form the oracle reports them.  No reduction
+arithmetic lives here."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+FLOAT = ("float32", "float64", "float16", "bfloat16")
+BITWISE = ("and", "or", "xor")
+TORCH = {"int32": torch.int32, "uint32": torch.uint32, "float32": torch.float32,
+         "float64": torch.float64, "float16": torch.float16, "bfloat16": torch.bfloat16}
+UNIT_ROUNDOFF = {"float32": 2.0 ** -24, "float64": 2.0 ** -53, "float16": 2.0 ** -24,
+                 "bfloat16": 2.0 ** -24}  # of the accumulator
+
+
+def gpu_available() -> bool:
+    return torch.cuda.is_available()
+
+
+def to_gpu(a: np.ndarray, dtype: str, pad_front: int = 0) -> torch.Tensor:
+    """Device tensor holding the bits of a (numpy storage of dtype), optionally
+    placed pad_front elements into a larger allocation (misaligned start)."""
+    a = np.ascontiguousarray(a)
+    if dtype in ("float16", "bfloat16"):
+        host = torch.from_numpy(a.view(np.int16).copy()).view(TORCH[dtype])
+    elif dtype == "uint32":
+        host = torch.from_numpy(a.view(np.int32).copy()).view(torch.uint32)
+    else:
+        host = torch.from_numpy(a.copy())
+    if pad_front:
+        big = torch.empty(a.size + pad_front, dtype=host.dtype, device="cuda")
+        dev = big[pad_front:]
+        dev.copy_(host.to("cuda"))
+        return dev
+    return host.to("cuda")
+
+
+def bits_of(t: torch.Tensor) -> int:
+    """Unsigned bit pattern of a 0-d device tensor."""
+    t = t.detach().reshape(1).cpu()
+    size = t.element_size()
+    view = {2: torch.int16, 4: torch.int32, 8: torch.int64}[size]
+    v = int(t.view(view).item())
+    return v % (1 << (8 * size))
+
+
+def value_of(t: torch.Tensor) -> float:
+    return float(t.detach().reshape(1).cpu().to(torch.float64).item())
+
+
+def same_float(a: float, b: float) -> bool:
+    """Bit-level agreement for min/max: equal values, same zero sign, or both NaN."""
+    if math.isnan(a) or math.isnan(b):
+        return math.isnan(a) and math.isnan(b)
+    return a == b and math.copysign(1.0, a) == math.copysign(1.0, b)
+
+
+def check_against_oracle(gpu_out: torch.Tensor, ref, x: np.ndarray, op: str, dtype: str,
+                         abs_sum: float | None = None, compensated: bool = False):
+    """Assert the GPU result matches the oracle to the bar for (op, dtype)."""
+    n = x.size
+    if dtype in ("int32", "uint32") or op in BITWISE:
+        got = bits_of(gpu_out)
+        assert got == ref, f"{op}/{dtype} n={n}: got {got:#x}, oracle {ref:#x}"
+        return
+    got = value_of(gpu_out)
+    if op in ("min", "max"):
+        assert same_float(got, ref), f"{op}/{dtype} n={n}: got {got!r}, oracle {ref!r}"
+    elif op == "sum":
+        tol = (2.0 ** -40 if compensated else 2.0 ** -20) * abs_sum
+        assert abs(got - ref) <= tol, f"sum/{dtype} n={n}: got {got!r}, exact {ref!r}, tol {tol!r}"
+    elif op == "prod":
+        u = UNIT_ROUNDOFF[dtype]
+        if ref == 0.0:
+            assert got == 0.0
+        else:
+            bound = 8.0 * math.sqrt(max(n, 1)) * u + 4.0 * u
+            assert got != 0.0 and math.copysign(1, got) == math.copysign(1, ref)
+            assert abs(math.log(got / ref)) <= bound, f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
+    else:
+        raise ValueError(op)

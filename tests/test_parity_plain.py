@@ -1,0 +1,187 @@
+"""Plain reduction: HIP path (through the C ABI) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import TORCH, check_against_oracle, gpu_available, same_float, to_gpu, value_of, bits_of
+from paper_1710_07358_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1710_07358_amd as rd  # noqa: E402
+
+OPS = ["sum", "prod", "min", "max", "and", "or", "xor"]
+SWEEP_N = [1, 31, 1023, 1025, 2 ** 20 + 7]
+
+
+def _run(x_np, op, dtype, pad=0, compensated=False):
+    x = to_gpu(x_np, dtype, pad_front=pad)
+    print(f"[plain] op={op} dtype={dtype} n={x_np.size} pad={pad}", flush=True)
+    out = rd.reduce_compensated(x) if compensated else rd.reduce(x, op)
+    torch.cuda.synchronize()
+    abs_sum = None
+    if op == "sum" and dtype not in ("int32", "uint32"):
+        ref, abs_sum = oracle.exact_sum(x_np, dtype)
+    else:
+        ref = oracle.reduce(x_np, op, dtype)
+    check_against_oracle(out, ref, x_np, op, dtype, abs_sum, compensated)
+    return out
+
+
+@pytest.mark.parametrize("op,dtype", [("sum", "float32"), ("max", "float32"), ("sum", "int32"),
+                                      ("xor", "int32"), ("min", "int32")])
+def test_plain_small_workload(op, dtype):
+    # 2^20 elements, the cache-resident workload
+    x = W.plain(2 ** 20, dtype, op, config=0)
+    _run(x, op, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64"])
+@pytest.mark.parametrize("op", OPS)
+def test_plain_sweep(op, dtype):
+    for n in SWEEP_N:
+        x = W.plain(n, dtype, op, config=1, salt=n)
+        _run(x, op, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["float16", "bfloat16"])
+@pytest.mark.parametrize("op", OPS)
+def test_plain_half_dtypes(op, dtype):
+    for n in [1, 7, 8, 9, 1025, 300_001]:
+        x = W.plain(n, dtype, op, config=1, salt=n)
+        _run(x, op, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16"])
+@pytest.mark.parametrize("op", ["sum", "max", "xor"])
+def test_plain_misaligned_base(op, dtype):
+    for pad in (1, 2, 3):
+        for n in (5, 1000, 65_537):
+            x = W.plain(n, dtype, op, config=1, salt=pad * 7 + n)
+            _run(x, op, dtype, pad=pad)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16"])
+@pytest.mark.parametrize("op", OPS)
+def test_plain_empty_is_identity(op, dtype):
+    x = np.zeros(0, dtype=W.STORAGE[dtype])
+    _run(x, op, dtype)
+
+
+def test_int_prod_odd_supplement():
+    for dtype in ("int32", "uint32"):
+        x = W.odd_int_supplement(2 ** 20 + 7, dtype)
+        _run(x, "prod", dtype)
+
+
+def test_float_specials():
+    nan, inf = math.nan, math.inf
+    cases = [
+        (np.array([1.0, nan, -5.0, 2.0], np.float32), "max"),
+        (np.array([1.0, nan, -5.0, 2.0], np.float32), "min"),
+        (np.array([-0.0, 0.0, -0.0], np.float32), "max"),
+        (np.array([0.0, -0.0, 0.0], np.float32), "min"),
+        (np.array([-inf, -inf], np.float64), "max"),
+        (np.array([inf, 1.0], np.float32), "sum"),
+    ]
+    for x, op in cases:
+        dtype = str(x.dtype)
+        out = rd.reduce(to_gpu(x, dtype), op)
+        torch.cuda.synchronize()
+        if op == "sum":
+            assert value_of(out) == math.inf
+        else:
+            assert same_float(value_of(out), oracle.reduce(x, op, dtype)), (x, op)
+    # NaN far into a long array, every lane layout
+    for at in (0, 5, 4095, 1_000_003):
+        x = W.plain(2 ** 20 + 9, "float32", "max", salt=at)
+        x[at] = np.float32(nan)
+        assert math.isnan(value_of(rd.reduce(to_gpu(x, "float32"), "max")))
+        assert math.isnan(value_of(rd.reduce(to_gpu(x, "float32"), "min")))
+
+
+def test_paper_footnote_example_on_gpu():
+    # 1.5 + 4^50 - 4^50: a plain float sum gives 0 or 1.5; compensated gives 1.5
+    x = np.array([1.5, 4.0 ** 50, -(4.0 ** 50)], np.float32)
+    plain = value_of(rd.reduce(to_gpu(x, "float32"), "sum"))
+    assert plain in (0.0, 1.5)
+    comp = value_of(rd.reduce_compensated(to_gpu(x, "float32")))
+    assert comp == 1.5
+
+
+def test_coverage_all_ones_every_config():
+    # every element is read exactly once, for every launch shape
+    n = 3 * 2 ** 20 + 13
+    x = np.ones(n, np.int32)
+    xg = to_gpu(x, "int32")
+    xs = to_gpu(x, "int32", pad_front=1)
+    try:
+        for block in (64, 256, 1024):
+            for unroll in (1, 2, 4, 8, 16):
+                for bpc in (1, 8):
+                    for nt in (0, 1):
+                        rd.config_force("plain", dict(block=block, unroll=unroll, blocks_per_cu=bpc, nontemporal=nt))
+                        assert bits_of(rd.reduce(xg, "sum")) == n, (block, unroll, bpc, nt)
+                        assert bits_of(rd.reduce(xs, "sum")) == n, (block, unroll, bpc, nt)
+    finally:
+        rd.config_force("plain", None)
+
+
+def test_config_invariance_int_results():
+    x = W.plain(2 ** 20 + 7, "int32", "xor", salt=3)
+    ref = oracle.reduce(x, "xor", "int32")
+    xg = to_gpu(x, "int32")
+    try:
+        for block, unroll in [(64, 1), (128, 16), (512, 4), (1024, 8)]:
+            rd.config_force("plain", dict(block=block, unroll=unroll, blocks_per_cu=4, nontemporal=0))
+            assert bits_of(rd.reduce(xg, "xor")) == ref
+    finally:
+        rd.config_force("plain", None)
+
+
+def test_float_sum_deterministic():
+    x = to_gpu(W.plain(2 ** 22 + 3, "float32", "sum", salt=9), "float32")
+    first = bits_of(rd.reduce(x, "sum"))
+    for _ in range(10):
+        assert bits_of(rd.reduce(x, "sum")) == first
+
+
+def test_permutation_invariance_ints_and_minmax():
+    rng = np.random.default_rng(5)
+    x = W.plain(100_003, "int32", "sum", salt=5)
+    xp = rng.permutation(x)
+    for op in ("sum", "min", "max", "xor", "and", "or"):
+        assert bits_of(rd.reduce(to_gpu(x, "int32"), op)) == bits_of(rd.reduce(to_gpu(xp, "int32"), op))
+    f = W.plain(100_003, "float32", "max", salt=5)
+    fp = rng.permutation(f)
+    for op in ("min", "max"):
+        assert bits_of(rd.reduce(to_gpu(f, "float32"), op)) == bits_of(rd.reduce(to_gpu(fp, "float32"), op))
+
+
+@pytest.mark.parametrize("op,dtype", [("sum", "float32"), ("max", "float32"), ("xor", "int32"),
+                                      ("min", "int32")])
+def test_full_size_2_28(op, dtype):
+    # the benchmarked size, in the launch configuration the benchmark uses
+    n = 2 ** 28
+    x = W.plain(n, dtype, op, config=1, salt=28)
+    _run(x, op, dtype)
+
+
+def test_explicit_workspace_and_stream():
+    ws = rd.Workspace()
+    s = torch.cuda.Stream()
+    x = W.plain(2 ** 20, "float32", "sum", config=0)
+    xg = to_gpu(x, "float32")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out = rd.reduce(xg, "sum", workspace=ws)
+    s.synchronize()
+    ref, a = oracle.exact_sum(x)
+    assert abs(value_of(out) - ref) <= 2.0 ** -20 * a
+    ws.close()
