@@ -77,6 +77,10 @@ typedef struct rd_config {
     int unroll;         /* independent 16-byte loads per work-item per step: 1, 2, 4, 8, 16 */
     int blocks_per_cu;  /* persistent grid = blocks_per_cu x compute units (capped by the work) */
     int nontemporal;    /* 1: stream the input with non-temporal loads */
+    int layout;         /* order in which work-groups visit chunks of block x unroll vectors:
+                           0 grid-stride (chunk b, b+G, ...), as in Section 2.3;
+                           1 grid-stride with the work-groups of one XCD on adjacent chunks;
+                           2 one contiguous run of chunks per work-group */
 } rd_config;
 
 /* Kinds of launch a configuration applies to. */
@@ -182,7 +186,7 @@ rd_status rd_config_force(rd_kind kind, const rd_config* cfg);
 
 /* Load a tuned table written by the autotuner (NULL restores the built-in
  * defaults).  Format: one line per entry,
- *   kind dtype_size op_class log2n_lo log2n_hi block unroll blocks_per_cu nontemporal
+ *   kind dtype_size op_class log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout
  * with op_class 0 = sum/prod, 1 = min/max, 2 = and/or/xor; '#' starts a comment. */
 rd_status rd_tune_load(const char* path);
 

@@ -29,7 +29,8 @@ _i64, _vp, _ci, _sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_si
 
 class RdConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("unroll", ctypes.c_int),
-                ("blocks_per_cu", ctypes.c_int), ("nontemporal", ctypes.c_int)]
+                ("blocks_per_cu", ctypes.c_int), ("nontemporal", ctypes.c_int),
+                ("layout", ctypes.c_int)]
 
 
 SIGNATURES = {

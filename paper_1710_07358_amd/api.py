@@ -199,14 +199,15 @@ def config_get(kind: str, dtype: torch.dtype, op: str, n: int) -> dict:
     c = N.RdConfig()
     N.check(N.lib().rd_config_get(KINDS[kind], DTYPES[dtype], _op(op), int(n), ctypes.byref(c)))
     return {"block": c.block, "unroll": c.unroll, "blocks_per_cu": c.blocks_per_cu,
-            "nontemporal": c.nontemporal}
+            "nontemporal": c.nontemporal, "layout": c.layout}
 
 
 def config_force(kind: str, cfg: dict | None) -> None:
     if cfg is None:
         N.check(N.lib().rd_config_force(KINDS[kind], None))
         return
-    c = N.RdConfig(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], int(cfg.get("nontemporal", 0)))
+    c = N.RdConfig(cfg["block"], cfg["unroll"], cfg["blocks_per_cu"], int(cfg.get("nontemporal", 0)),
+                   int(cfg.get("layout", 0)))
     N.check(N.lib().rd_config_force(KINDS[kind], ctypes.byref(c)))
 
 

@@ -75,13 +75,12 @@ rd_status current_device(int* dev, DeviceInfo* info) {
 constexpr size_t kAlign = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Layout: [ticket | per-wavefront counters] (zeroed region), partials, carries.
+// Layout: [ticket, status | per-wavefront counters], partial slots, carry
+// slots.  All of it is zero between launches.
 size_t counters_bytes() { return round_up(kAlign + (size_t)rd::kMaxSegWaves * 4, kAlign); }
-
-size_t workspace_bytes() {
-  return counters_bytes() + round_up((size_t)rd::kMaxGrid * 16, kAlign) +
-         round_up((size_t)rd::kMaxSegWaves * 2 * 16, kAlign);
-}
+size_t partial_bytes() { return round_up((size_t)rd::kMaxGrid * rd::kPartialWords * 8, kAlign); }
+size_t carry_bytes() { return round_up((size_t)rd::kMaxSegWaves * 2 * rd::kCarryWords * 8, kAlign); }
+size_t workspace_bytes() { return counters_bytes() + partial_bytes() + carry_bytes(); }
 
 rd_status create_workspace(rd_workspace** out, int device) {
   int prev = -1;
@@ -93,7 +92,7 @@ rd_status create_workspace(rd_workspace** out, int device) {
   ws->bytes = workspace_bytes();
   ws->mem = nullptr;
   e = hipMalloc(&ws->mem, ws->bytes);
-  if (e == hipSuccess) e = hipMemset(ws->mem, 0, ws->bytes);  // counters start at zero
+  if (e == hipSuccess) e = hipMemset(ws->mem, 0, ws->bytes);  // counters and slots start at zero
   if (device != prev) (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     if (ws->mem) (void)hipFree(ws->mem);
@@ -106,10 +105,10 @@ rd_status create_workspace(rd_workspace** out, int device) {
   s.ticket = (unsigned*)p;
   s.counters = (unsigned*)(p + kAlign);
   p += counters_bytes();
-  s.partial = p;
+  s.partial = (uint64_t*)p;
   s.partial_cap = rd::kMaxGrid;
-  p += round_up((size_t)rd::kMaxGrid * 16, kAlign);
-  s.carry = p;
+  p += partial_bytes();
+  s.carry = (uint64_t*)p;
   s.carry_cap = (int64_t)rd::kMaxSegWaves * 2;
   *out = ws;
   return RD_OK;
@@ -162,15 +161,16 @@ int op_class(rd_op op) {
 }
 
 std::vector<TuneEntry> builtin_table() {
-  // Defaults before tuning: 256 work-items, U = 8 x 16-byte loads, 8 groups
-  // per CU, non-temporal streaming for inputs far beyond the 256 MB MALL.
+  // Defaults before tuning (measured on MI355X for float32 sums): few
+  // resident wavefronts per CU stream best; non-temporal loads and XCD-grouped
+  // chunks for inputs far beyond the 256 MB MALL.
   std::vector<TuneEntry> t;
   for (int kind = 0; kind < 3; ++kind)
     for (int es : {2, 4, 8})
       for (int oc = 0; oc < 3; ++oc) {
-        t.push_back({kind, es, oc, 0, 17, {256, 2, 8, 0}});
-        t.push_back({kind, es, oc, 18, 23, {256, 4, 8, 0}});
-        t.push_back({kind, es, oc, 24, 62, {256, 8, 8, 1}});
+        t.push_back({kind, es, oc, 0, 17, {256, 2, 4, 0, 0}});
+        t.push_back({kind, es, oc, 18, 23, {256, 4, 2, 0, 1}});
+        t.push_back({kind, es, oc, 24, 62, {512, 2, 2, 1, 1}});
       }
   return t;
 }
@@ -191,13 +191,14 @@ rd_config choose_config(rd_kind kind, rd_dtype dt, rd_op op, int64_t n) {
   const int es = (int)rd_dtype_size(dt), oc = op_class(op), l = log2_ceil(n);
   for (const TuneEntry& e : g_table)
     if (e.kind == (int)kind && e.esize == es && e.opclass == oc && l >= e.lo && l <= e.hi) return e.cfg;
-  return rd_config{256, 8, 8, 0};
+  return rd_config{256, 8, 2, 0, 0};
 }
 
 bool valid_config(const rd_config& c) {
   const bool u_ok = c.unroll == 1 || c.unroll == 2 || c.unroll == 4 || c.unroll == 8 || c.unroll == 16;
   return c.block >= 64 && c.block <= 1024 && c.block % 64 == 0 && u_ok && c.blocks_per_cu >= 1 &&
-         c.blocks_per_cu <= 64 && (c.nontemporal == 0 || c.nontemporal == 1);
+         c.blocks_per_cu <= 64 && (c.nontemporal == 0 || c.nontemporal == 1) && c.layout >= 0 &&
+         c.layout <= 2;
 }
 
 // Persistent grid: min(work chunks, blocks_per_cu x CUs, workspace capacity).
@@ -206,7 +207,7 @@ rd::Launch plan(const rd_config& c, int64_t nvec, int cus, int cap) {
   int64_t chunks = (nvec + per_chunk - 1) / per_chunk;
   int64_t g = std::min<int64_t>((int64_t)c.blocks_per_cu * cus, cap);
   g = std::max<int64_t>(1, std::min(g, chunks));
-  return rd::Launch{c.block, (int)g, c.unroll, c.nontemporal != 0};
+  return rd::Launch{c.block, (int)g, c.unroll, c.nontemporal != 0, c.layout};
 }
 
 bool valid_dtype(rd_dtype dt) { return dt >= RD_I32 && dt <= RD_BF16; }
@@ -299,7 +300,7 @@ rd_status rd_workspace_destroy(rd_workspace* ws) {
 
 rd_status rd_workspace_reset(rd_workspace* ws, void* stream) {
   if (!ws) return fail(RD_ERR_INVALID_ARG, "rd_workspace_reset: ws is NULL");
-  hipError_t e = hipMemsetAsync(ws->scratch.ticket, 0, counters_bytes(), (hipStream_t)stream);
+  hipError_t e = hipMemsetAsync(ws->mem, 0, ws->bytes, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "hipMemsetAsync");
 }
 
@@ -376,7 +377,7 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
   const int waves_per_block = cfg.block / 64;
   int grid = std::min(cfg.blocks_per_cu * info.cus, rd::kMaxSegWaves / waves_per_block);
   grid = std::max(grid, 1);
-  const rd::Launch l{cfg.block, grid, cfg.unroll, cfg.nontemporal != 0};
+  const rd::Launch l{cfg.block, grid, cfg.unroll, cfg.nontemporal != 0, cfg.layout};
   hipError_t e = fn(x, offsets, nseg, out, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_segmented_reduce launch");
 }
@@ -436,8 +437,8 @@ rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_confi
 rd_status rd_config_force(rd_kind kind, const rd_config* cfg) {
   if (kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
   if (cfg && !valid_config(*cfg))
-    return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d",
-                cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal);
+    return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d layout %d",
+                cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal, cfg->layout);
   std::lock_guard<std::mutex> lock(g_mu);
   g_forced[kind] = cfg != nullptr;
   if (cfg) g_force_cfg[kind] = *cfg;
@@ -460,10 +461,10 @@ rd_status rd_tune_load(const char* path) {
     char* hash = std::strchr(line, '#');
     if (hash) *hash = 0;
     TuneEntry e;
-    int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &e.kind, &e.esize, &e.opclass, &e.lo, &e.hi,
-                        &e.cfg.block, &e.cfg.unroll, &e.cfg.blocks_per_cu, &e.cfg.nontemporal);
+    int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.kind, &e.esize, &e.opclass, &e.lo, &e.hi,
+                        &e.cfg.block, &e.cfg.unroll, &e.cfg.blocks_per_cu, &e.cfg.nontemporal, &e.cfg.layout);
     if (k <= 0) continue;
-    if (k != 9 || e.kind < 0 || e.kind > 2 || !valid_config(e.cfg)) {
+    if (k != 10 || e.kind < 0 || e.kind > 2 || !valid_config(e.cfg)) {
       std::fclose(f);
       return fail(RD_ERR_INVALID_ARG, "rd_tune_load: %s:%d: malformed entry", path, lineno);
     }

@@ -10,8 +10,8 @@
 //   barrier-free LDS tree of Section 3 is only safe inside one wavefront, so
 //   the cross-wavefront step keeps one barrier.
 // * Grid stage (stage 2 of Section 2.3, done in the same launch): each
-//   work-group publishes one partial, and the last one to arrive -- found
-//   with an agent-scope acquire/release counter -- folds them in index order.
+//   work-group publishes one partial, and the last one to arrive at a
+//   counter folds them in index order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -115,22 +115,29 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
 template <Store S, Op O> struct Red {
   using T = typename Stored<S>::T;
   static constexpr bool half = (S == Store::F16 || S == Store::BF16);
-  // accumulator type
+  // accumulator type.  Float products accumulate in float64: a float32
+  // product of factors near 1 hovers around 1.0, where round-to-nearest
+  // ties are broken one way by the tiny second-order term, so float32
+  // accumulation drifts linearly in n (about 6% at n = 2^28).
   using Acc = typename std::conditional<
-      S == Store::F32 || half, float,
-      typename std::conditional<S == Store::F64, double,
-                                typename std::conditional<S == Store::U16, uint32_t, T>::type>::type>::type;
+      (S == Store::F32 || half) && O == Op::Prod, double,
+      typename std::conditional<
+          S == Store::F32 || half, float,
+          typename std::conditional<S == Store::F64, double,
+                                    typename std::conditional<S == Store::U16, uint32_t, T>::type>::type>::type>::type;
   // output element type
   using Out = typename std::conditional<
       half && (O == Op::Min || O == Op::Max), uint16_t,
-      typename std::conditional<S == Store::U16, uint16_t, Acc>::type>::type;
+      typename std::conditional<S == Store::U16, uint16_t,
+                                typename std::conditional<(S == Store::F32 || half) && O == Op::Prod, float,
+                                                          Acc>::type>::type>::type;
   using C = Combiner<O, Acc>;
 
   static __device__ __forceinline__ Acc identity() { return C::identity(); }
   static __device__ __forceinline__ Acc apply(Acc a, Acc b) { return C::apply(a, b); }
   static __device__ __forceinline__ Acc convert(T v) {
-    if constexpr (S == Store::F16) return f16_to_f32(v);
-    else if constexpr (S == Store::BF16) return bf16_to_f32(v);
+    if constexpr (S == Store::F16) return (Acc)f16_to_f32(v);
+    else if constexpr (S == Store::BF16) return (Acc)bf16_to_f32(v);
     else if constexpr (S == Store::U16) return (uint32_t)v;  // upper half ignored by finalize
     else return v;
   }
@@ -140,7 +147,7 @@ template <Store S, Op O> struct Red {
     else if constexpr (S == Store::BF16 && (O == Op::Min || O == Op::Max))
       return (uint16_t)(__builtin_bit_cast(uint32_t, a) >> 16);  // exact: low half is zero
     else if constexpr (S == Store::U16) return (uint16_t)a;
-    else return a;
+    else return (Out)a;  // float64 product -> float32: one rounding
   }
 };
 
@@ -279,42 +286,62 @@ __device__ __forceinline__ float wave_reverse(float v) {
 
 // ------------------------------------------------------------------ grid stage
 
-// Publish this work-group's partial and learn whether it is the last one.
-// Release: the partial (written by thread 0 before) is made visible at agent
-// scope before the counter increment; the last work-group acquires at agent
-// scope, so it sees every other XCD's partial despite the per-XCD L2 caches.
+// Publishing a value to the work-group that finishes the reduction.  Each
+// 32-bit piece of the value travels in its own 64-bit agent-scope atomic word
+// next to a nonzero tag, so a reader that sees the tag sees this launch's
+// piece: no ordering between different words is needed, hence no agent-scope
+// release/acquire fences (on gfx950 those write back and invalidate the whole
+// L2 of the XCD -- about 20 us per launch when every work-group does it).
+// The reader clears the words after use, which re-arms the slot for the next
+// launch or graph replay.
+constexpr uint64_t kTag = 1ull << 32;
+constexpr int kMaxSpin = 1 << 20;  // bounded wait; a correct launch never comes close
+
+template <class A> __device__ __forceinline__ void publish(uint64_t* slot, A v) {
+  struct P { uint32_t w[sizeof(A) / 4]; };
+  const P p = __builtin_bit_cast(P, v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(A) / 4); ++i)
+    __hip_atomic_store(slot + i, kTag | (uint64_t)p.w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every word of the slot carries the tag, clear it, return the
+// value.  A wait that runs out (impossible unless the launch is broken) sets
+// *status and returns what the words hold.
+template <class A> __device__ __forceinline__ A collect(uint64_t* slot, unsigned* status) {
+  struct P { uint32_t w[sizeof(A) / 4]; };
+  P p;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(A) / 4); ++i) {
+    uint64_t word = __hip_atomic_load(slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int spin = 0; !(word & kTag) && spin < kMaxSpin; ++spin) {
+      __builtin_amdgcn_s_sleep(2);
+      word = __hip_atomic_load(slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!(word & kTag)) __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    p.w[i] = (uint32_t)word;
+    __hip_atomic_store(slot + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return __builtin_bit_cast(A, p);
+}
+
+// Count this work-group in and learn whether it is the last of nblocks.
+// The counter only elects the finisher; the data arrive through publish /
+// collect, so a relaxed agent-scope increment is enough.  The finisher
+// re-zeroes the counter for the next launch.
 __device__ __forceinline__ bool arrive_last(unsigned* ticket, unsigned nblocks, int* lds_flag) {
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    bool last = (prev == nblocks - 1);
-    if (last) {
-      __threadfence();
-      __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next launch / replay
-    }
+    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool last = (prev == nblocks - 1);
+    if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *lds_flag = last ? 1 : 0;
   }
   __syncthreads();
   return *lds_flag != 0;
 }
 
-// Coherent (L2-bypassing at agent scope) load of a value another work-group published.
-template <class A> __device__ __forceinline__ A load_published(const A* p) {
-  if constexpr (sizeof(A) == 4) {
-    uint32_t b = __hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_bit_cast(A, b);
-  } else if constexpr (sizeof(A) == 8) {
-    uint64_t b = __hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_bit_cast(A, b);
-  } else {
-    struct W { uint64_t a, b; };
-    const uint64_t* q = (const uint64_t*)p;
-    W w;
-    w.a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    w.b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_bit_cast(A, w);
-  }
-}
+// Words of one published slot for accumulator type A.
+template <class A> constexpr int slot_words() { return (int)(sizeof(A) / 4); }
 
 // ------------------------------------------------------------------ double-double
 

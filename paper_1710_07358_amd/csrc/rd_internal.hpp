@@ -16,18 +16,23 @@ struct Launch {
   int grid;
   int unroll;
   bool nontemporal;
+  int layout;  // rd_config::layout
 };
 
-// Device scratch handed to a kernel: a completion counter and room for one
-// partial per work-group (16 bytes each) and the segmented carries.
+// Device scratch handed to a kernel.  Published values live in tagged
+// 64-bit words (one per 32 bits of value); every word is zero between
+// launches, and so are the counters.
 struct Scratch {
-  unsigned* ticket;     // zero between launches; the last work-group re-zeroes it
-  unsigned* counters;   // segmented: one per wavefront, zero between launches
-  void* partial;        // >= grid * 16 bytes
-  void* carry;          // segmented: >= 2 * wavefronts * 16 bytes
-  int64_t partial_cap;  // entries of 16 bytes
-  int64_t carry_cap;    // carry entries of 16 bytes
+  unsigned* ticket;     // [0]: completion counter; [1]: status (nonzero: a bounded wait ran out)
+  unsigned* counters;   // segmented: one per wavefront
+  uint64_t* partial;    // kPartialWords words per work-group
+  uint64_t* carry;      // segmented: kCarryWords words per slot, 2 slots per wavefront
+  int64_t partial_cap;  // work-groups
+  int64_t carry_cap;    // carry slots
 };
+
+constexpr int kPartialWords = 4;  // up to 16-byte partials (double-double)
+constexpr int kCarryWords = 2;    // up to 8-byte accumulators
 
 // Upper bounds the workspace is sized for.
 constexpr int kMaxGrid = 8192;

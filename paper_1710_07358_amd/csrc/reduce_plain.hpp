@@ -19,12 +19,32 @@
 
 namespace rd {
 
+// The chunks (of block x U vectors) a work-group visits: first, first + step,
+// ... below end.  Layout 0 is the grid-stride order of Section 2.3; layout 1
+// renumbers work-groups so that those dispatched to one XCD (work-groups are
+// dealt round-robin to the 8 XCDs) take adjacent chunks; layout 2 gives each
+// work-group one contiguous run.
+struct ChunkWalk {
+  int64_t first, end, step;
+};
+__device__ __forceinline__ ChunkWalk chunk_walk(int layout, int64_t nchunks) {
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  if (layout == 2) {
+    const int64_t per = nchunks / G, extra = nchunks % G;
+    const int64_t first = b * per + (b < extra ? b : extra);
+    return ChunkWalk{first, first + per + (b < extra ? 1 : 0), 1};
+  }
+  int64_t lb = b;
+  if (layout == 1 && (G & 7) == 0) lb = (b & 7) * (G >> 3) + (b >> 3);
+  return ChunkWalk{lb, nchunks, G};
+}
+
 template <class R, int U, bool NT>
 __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __restrict__ x,
                                                       int64_t n,
-                                                      typename R::Acc* __restrict__ partial,
+                                                      uint64_t* __restrict__ partial,
                                                       unsigned* __restrict__ ticket,
-                                                      typename R::Out* __restrict__ out) {
+                                                      typename R::Out* __restrict__ out, int layout) {
   using T = typename R::T;
   using A = typename R::Acc;
   constexpr int V = 16 / (int)sizeof(T);
@@ -49,7 +69,8 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
 
   const int64_t step = B * U;  // vectors per chunk
   const int64_t nfull = nvec / step;
-  for (int64_t c = blockIdx.x; c < nfull; c += G) {
+  const ChunkWalk walk = chunk_walk(layout, nfull);
+  for (int64_t c = walk.first; c < walk.end; c += walk.step) {
     const u32x4* p = xv + c * step + tid;
     u32x4 v[U];
 #pragma unroll
@@ -81,11 +102,12 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
 
   auto comb = [](A a, A b) { return R::apply(a, b); };
   A blk = block_reduce(mine, R::identity(), comb, lds);
-  if (tid == 0) partial[blockIdx.x] = blk;
+  constexpr int SW = slot_words<A>();
+  if (tid == 0) publish(partial + blockIdx.x * SW, blk);
 
   if (arrive_last(ticket, (unsigned)G, &last_flag)) {
     A r = R::identity();
-    for (int64_t b = tid; b < G; b += B) r = R::apply(r, load_published(partial + b));
+    for (int64_t b = tid; b < G; b += B) r = R::apply(r, collect<A>(partial + b * SW, ticket + 1));
     r = block_reduce(r, R::identity(), comb, lds);
     if (tid == 0) *out = R::finalize(r);
   }
@@ -95,10 +117,11 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
 // float32 -- TwoSum keeps the rounding error of each addition exactly, and
 // c collects those errors.  Pairs leave the work-item as double-double and
 // are merged in float64 (DPP, LDS and the last-block-done fold).
+static_assert(sizeof(dd) / 4 <= kPartialWords, "partial slot too small");
 template <Store S, int U, bool NT>
 __global__ __launch_bounds__(1024) void reduce_compensated_kernel(
-    const typename Stored<S>::T* __restrict__ x, int64_t n, dd* __restrict__ partial,
-    unsigned* __restrict__ ticket, double* __restrict__ out) {
+    const typename Stored<S>::T* __restrict__ x, int64_t n, uint64_t* __restrict__ partial,
+    unsigned* __restrict__ ticket, double* __restrict__ out, int layout) {
 #pragma clang fp contract(off)
   using T = typename Stored<S>::T;
   using R = Red<S, Op::Sum>;
@@ -129,7 +152,8 @@ __global__ __launch_bounds__(1024) void reduce_compensated_kernel(
 
   const int64_t step = B * U;
   const int64_t nfull = nvec / step;
-  for (int64_t ch = blockIdx.x; ch < nfull; ch += G) {
+  const ChunkWalk walk = chunk_walk(layout, nfull);
+  for (int64_t ch = walk.first; ch < walk.end; ch += walk.step) {
     const u32x4* p = xv + ch * step + tid;
     u32x4 v[U];
 #pragma unroll
@@ -158,10 +182,11 @@ __global__ __launch_bounds__(1024) void reduce_compensated_kernel(
   auto comb = [](dd a, dd b) { return dd_add(a, b); };
   const dd zero{0.0, 0.0};
   dd blk = block_reduce(mine, zero, comb, lds);
-  if (tid == 0) partial[blockIdx.x] = blk;
+  constexpr int SW = slot_words<dd>();
+  if (tid == 0) publish(partial + blockIdx.x * SW, blk);
   if (arrive_last(ticket, (unsigned)G, &last_flag)) {
     dd r = zero;
-    for (int64_t b = tid; b < G; b += B) r = dd_add(r, load_published(partial + b));
+    for (int64_t b = tid; b < G; b += B) r = dd_add(r, collect<dd>(partial + b * SW, ticket + 1));
     r = block_reduce(r, zero, comb, lds);
     if (tid == 0) *out = r.hi + r.lo;
   }
@@ -173,8 +198,8 @@ template <class R, int U, bool NT>
 hipError_t launch_plain(const void* x, int64_t n, void* out, const Scratch& ws, const Launch& l,
                         hipStream_t s) {
   hipLaunchKernelGGL((reduce_kernel<R, U, NT>), dim3(l.grid), dim3(l.block), 0, s,
-                     (const typename R::T*)x, n, (typename R::Acc*)ws.partial, ws.ticket,
-                     (typename R::Out*)out);
+                     (const typename R::T*)x, n, ws.partial, ws.ticket,
+                     (typename R::Out*)out, l.layout);
   return hipGetLastError();
 }
 
@@ -182,7 +207,8 @@ template <Store S, int U, bool NT>
 hipError_t launch_comp(const void* x, int64_t n, void* out, const Scratch& ws, const Launch& l,
                        hipStream_t s) {
   hipLaunchKernelGGL((reduce_compensated_kernel<S, U, NT>), dim3(l.grid), dim3(l.block), 0, s,
-                     (const typename Stored<S>::T*)x, n, (dd*)ws.partial, ws.ticket, (double*)out);
+                     (const typename Stored<S>::T*)x, n, ws.partial, ws.ticket, (double*)out,
+                     l.layout);
   return hipGetLastError();
 }
 

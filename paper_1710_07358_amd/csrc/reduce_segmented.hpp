@@ -59,8 +59,9 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
                                                          const int64_t* __restrict__ offsets,
                                                          int64_t nseg,
                                                          typename R::Out* __restrict__ out,
-                                                         typename R::Acc* __restrict__ carry,
-                                                         unsigned* __restrict__ counters) {
+                                                         uint64_t* __restrict__ carry,
+                                                         unsigned* __restrict__ counters,
+                                                         unsigned* __restrict__ status) {
   using T = typename R::T;
   using A = typename R::Acc;
   constexpr int V = 16 / (int)sizeof(T);
@@ -158,26 +159,27 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
       if (lane == 0) out[sid] = R::finalize(piece);
       return;
     }
+    constexpr int SW = slot_words<A>();
+    static_assert(SW <= kCarryWords, "carry slot too small");
     const int64_t slot = (sb < r0) ? 2 * w : 2 * w + 1;
-    if (lane == 0) carry[slot] = piece;
     const int64_t wf = P.wave_of(sb), wl = P.wave_of(se - 1);
     const unsigned np = (unsigned)(wl - wf + 1);
     unsigned prev = 0;
     if (lane == 0) {
-      __threadfence();
-      prev = __hip_atomic_fetch_add(counters + wf, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      publish(carry + slot * SW, piece);
+      prev = __hip_atomic_fetch_add(counters + wf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     prev = (unsigned)__builtin_amdgcn_readfirstlane((int)prev);
     if (prev + 1 != np) return;
-    __threadfence();
-    // Last piece in: fold wf's tail slot and the head slots of wf+1..wl, in order.
+    // Last piece counted in: fold wf's tail slot and the head slots of
+    // wf+1..wl, in that order, each lane waiting for its slot's tag.
     A total = R::identity();
     for (int64_t base = 0; base < (int64_t)np; base += 64) {
       const int64_t q = base + lane;
       A v = R::identity();
       if (q < (int64_t)np) {
         const int64_t ww = wf + q;
-        v = load_published(carry + (q == 0 ? 2 * ww + 1 : 2 * ww));
+        v = collect<A>(carry + (q == 0 ? 2 * ww + 1 : 2 * ww) * SW, status);
       }
       total = R::apply(total, wave_reduce_r<R>(v));
     }
@@ -274,7 +276,7 @@ hipError_t launch_seg(const void* x, const int64_t* offsets, int64_t nseg, void*
                       const Scratch& ws, const Launch& l, hipStream_t s) {
   hipLaunchKernelGGL((segmented_kernel<R, U, NT>), dim3(l.grid), dim3(l.block), 0, s,
                      (const typename R::T*)x, offsets, nseg, (typename R::Out*)out,
-                     (typename R::Acc*)ws.carry, ws.counters);
+                     ws.carry, ws.counters, ws.ticket + 1);
   return hipGetLastError();
 }
 

@@ -86,10 +86,9 @@ __device__ __forceinline__ void store_stripe(float* __restrict__ row, int64_t co
 }
 
 struct ProdAcc {  // chunk-level product state (16 bytes, combinable by DPP)
-  float p;        // product of nonzero entries
+  double p;       // product of nonzero entries (float64: see the plain kernel's traits)
   int32_t zeros;
   int32_t first;  // smallest zero column, INT32_MAX if none
-  int32_t pad;
 };
 
 }  // namespace
@@ -199,14 +198,14 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       ProdHeader* hdr = (ProdHeader*)saved;
       float* chunk_prod = (float*)((char*)saved + rows * (int64_t)sizeof(ProdHeader));
       int32_t zeros = 0, first = INT32_MAX;
-      float pnz = 1.0f;
+      double pnz = 1.0;
       auto comb = [](ProdAcc a, ProdAcc b) {
-        return ProdAcc{a.p * b.p, a.zeros + b.zeros, a.first < b.first ? a.first : b.first, 0};
+        return ProdAcc{a.p * b.p, a.zeros + b.zeros, a.first < b.first ? a.first : b.first};
       };
       for (int64_t k = 0; k < nch; ++k) {
         const int64_t c0 = k * kChunk;
         const bool full = c0 + kChunk <= cols;
-        float p = 1.0f;
+        double p = 1.0;
         int32_t z = 0, fz = INT32_MAX;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -216,14 +215,14 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const bool zero = (v[e] == 0.0f);
-            p = zero ? p : p * v[e];
+            p = zero ? p : p * (double)v[e];
             z += zero ? 1 : 0;
             fz = (zero && fz == INT32_MAX) ? (int32_t)(col + e) : fz;
           }
         }
-        const ProdAcc tot = block_reduce(ProdAcc{p, z, fz, 0}, ProdAcc{1.0f, 0, INT32_MAX, 0}, comb, lds_p);
+        const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0, INT32_MAX}, comb, lds_p);
         if (t == 0) {
-          chunk_prod[r * nch + k] = tot.p;
+          chunk_prod[r * nch + k] = (float)tot.p;
           zeros += tot.zeros;
           first = tot.first < first ? tot.first : first;
           pnz *= tot.p;
@@ -231,8 +230,8 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
         __syncthreads();
       }
       if (t == 0) {
-        hdr[r] = ProdHeader{zeros, first == INT32_MAX ? -1 : first, pnz, 0.0f};
-        y[r] = zeros > 0 ? 0.0f * pnz : pnz;
+        hdr[r] = ProdHeader{zeros, first == INT32_MAX ? -1 : first, (float)pnz, 0.0f};
+        y[r] = zeros > 0 ? 0.0f * (float)pnz : (float)pnz;
       }
     }
   }

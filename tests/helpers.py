@@ -14,8 +14,6 @@ FLOAT = ("float32", "float64", "float16", "bfloat16")
 BITWISE = ("and", "or", "xor")
 TORCH = {"int32": torch.int32, "uint32": torch.uint32, "float32": torch.float32,
          "float64": torch.float64, "float16": torch.float16, "bfloat16": torch.bfloat16}
-UNIT_ROUNDOFF = {"float32": 2.0 ** -24, "float64": 2.0 ** -53, "float16": 2.0 ** -24,
-                 "bfloat16": 2.0 ** -24}  # of the accumulator
 
 
 def gpu_available() -> bool:
@@ -75,12 +73,14 @@ def check_against_oracle(gpu_out: torch.Tensor, ref, x: np.ndarray, op: str, dty
         tol = (2.0 ** -40 if compensated else 2.0 ** -20) * abs_sum
         assert abs(got - ref) <= tol, f"sum/{dtype} n={n}: got {got!r}, exact {ref!r}, tol {tol!r}"
     elif op == "prod":
-        u = UNIT_ROUNDOFF[dtype]
+        # Float products accumulate in float64 whatever the input dtype: any
+        # product tree of n factors is within (1+2^-53)^(n-1) - 1 of the exact
+        # product, then float32 outputs add one rounding (2^-24).
+        out_u = 0.0 if dtype == "float64" else 2.0 ** -24
+        bound = (max(n - 1, 0) * 2.0 ** -53) * 1.001 + out_u
         if ref == 0.0:
             assert got == 0.0
         else:
-            bound = 8.0 * math.sqrt(max(n, 1)) * u + 4.0 * u
-            assert got != 0.0 and math.copysign(1, got) == math.copysign(1, ref)
-            assert abs(math.log(got / ref)) <= bound, f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
+            assert abs(got - ref) <= bound * abs(ref), f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
     else:
         raise ValueError(op)

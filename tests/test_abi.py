@@ -117,25 +117,27 @@ def test_saved_bytes(N):
 
 def test_config_force_and_tune_table(N, tmp_path):
     lib = N.lib()
-    cfg = N.RdConfig(256, 3, 8, 0)  # unroll 3 has no kernel
+    cfg = N.RdConfig(256, 3, 8, 0, 0)  # unroll 3 has no kernel
     assert lib.rd_config_force(N.RD_KIND_PLAIN, ctypes.byref(cfg)) == N.RD_ERR_INVALID_ARG
-    cfg = N.RdConfig(96, 4, 8, 0)  # block not a multiple of 64
+    cfg = N.RdConfig(96, 4, 8, 0, 0)  # block not a multiple of 64
     assert lib.rd_config_force(N.RD_KIND_PLAIN, ctypes.byref(cfg)) == N.RD_ERR_INVALID_ARG
-    good = N.RdConfig(512, 16, 2, 1)
+    good = N.RdConfig(512, 16, 2, 1, 2)
     assert lib.rd_config_force(N.RD_KIND_PLAIN, ctypes.byref(good)) == N.RD_OK
     got = N.RdConfig()
     assert lib.rd_config_get(N.RD_KIND_PLAIN, N.RD_F32, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
-    assert (got.block, got.unroll, got.blocks_per_cu, got.nontemporal) == (512, 16, 2, 1)
+    assert (got.block, got.unroll, got.blocks_per_cu, got.nontemporal, got.layout) == (512, 16, 2, 1, 2)
+    bad_layout = N.RdConfig(256, 4, 1, 0, 3)
+    assert lib.rd_config_force(N.RD_KIND_PLAIN, ctypes.byref(bad_layout)) == N.RD_ERR_INVALID_ARG
     assert lib.rd_config_force(N.RD_KIND_PLAIN, None) == N.RD_OK
     table = tmp_path / "tune.txt"
-    table.write_text("# kind esize opclass lo hi block unroll bpc nt\n0 4 0 20 30 1024 4 2 1\n")
+    table.write_text("# kind esize opclass lo hi block unroll bpc nt layout\n0 4 0 20 30 1024 4 2 1 1\n")
     assert lib.rd_tune_load(str(table).encode()) == N.RD_OK
     assert lib.rd_config_get(N.RD_KIND_PLAIN, N.RD_F32, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
-    assert (got.block, got.unroll, got.blocks_per_cu, got.nontemporal) == (1024, 4, 2, 1)
-    assert lib.rd_config_get(N.RD_KIND_PLAIN, N.RD_F64, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
+    assert (got.block, got.unroll, got.blocks_per_cu, got.nontemporal, got.layout) == (1024, 4, 2, 1, 1)
+    assert lib.rd_config_get(N.RD_KIND_PLAIN, N.RD_F64, N.RD_SUM, 1 << 10, ctypes.byref(got)) == N.RD_OK
     assert got.block == 256  # uncovered entries keep the defaults
     bad = tmp_path / "bad.txt"
-    bad.write_text("0 4 0 20 30 1024 5 2 1\n")
+    bad.write_text("0 4 0 20 30 1024 5 2 1 0\n")
     assert lib.rd_tune_load(str(bad).encode()) == N.RD_ERR_INVALID_ARG
     assert lib.rd_tune_load(None) == N.RD_OK
 

@@ -124,11 +124,14 @@ def test_coverage_all_ones_every_config():
     try:
         for block in (64, 256, 1024):
             for unroll in (1, 2, 4, 8, 16):
-                for bpc in (1, 8):
+                for bpc in (1, 3, 8):
                     for nt in (0, 1):
-                        rd.config_force("plain", dict(block=block, unroll=unroll, blocks_per_cu=bpc, nontemporal=nt))
-                        assert bits_of(rd.reduce(xg, "sum")) == n, (block, unroll, bpc, nt)
-                        assert bits_of(rd.reduce(xs, "sum")) == n, (block, unroll, bpc, nt)
+                        for layout in (0, 1, 2):
+                            cfg = dict(block=block, unroll=unroll, blocks_per_cu=bpc, nontemporal=nt,
+                                       layout=layout)
+                            rd.config_force("plain", cfg)
+                            assert bits_of(rd.reduce(xg, "sum")) == n, cfg
+                            assert bits_of(rd.reduce(xs, "sum")) == n, cfg
     finally:
         rd.config_force("plain", None)
 
@@ -185,3 +188,19 @@ def test_explicit_workspace_and_stream():
     ref, a = oracle.exact_sum(x)
     assert abs(value_of(out) - ref) <= 2.0 ** -20 * a
     ws.close()
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64", "float16", "bfloat16"])
+def test_float_prod_powers_of_two_exact(dtype):
+    # ones with planted powers of two: every partial product is an exact power
+    # of two, so any grouping gives the exact product (bit-exact coverage pin)
+    rng = np.random.default_rng(77)
+    for n in (1, 33, 4099, 2 ** 20 + 5):
+        e = np.zeros(n, np.int64)
+        at = rng.choice(n, size=min(n, 60), replace=False)
+        e[at] = rng.choice([-3, -2, -1, 1, 2, 3], size=at.size)
+        x = W.to_storage(np.exp2(e.astype(np.float64)), dtype)
+        out = rd.reduce(to_gpu(x, dtype), "prod")
+        expect = 2.0 ** int(e.sum())
+        assert oracle.reduce(x, "prod", dtype) == expect
+        assert value_of(out) == expect, (dtype, n)
