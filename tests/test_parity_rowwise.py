@@ -1,0 +1,201 @@
+"""Row-wise forward and hand-written backward: HIP path against the CPU
+oracle's definitions, FP64 finite differences, and the autograd Function."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import gpu_available
+from paper_1710_07358_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not gpu_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1710_07358_amd as rd  # noqa: E402
+
+OPS = ["sum", "max", "min", "prod"]
+SHAPES = [(1, 1), (3, 5), (7, 4099), (2, 16384), (5, 16385), (4, 40_000), (3, 65_536 + 3)]
+
+
+def prod_grad_ok(got, ref):
+    scale = np.max(np.abs(ref), axis=1, keepdims=True)
+    return np.all(np.abs(got - ref) <= 2.0 ** -12 * np.abs(ref) + 2.0 ** -40 * scale)
+
+
+def check_forward(x_np, op, y, saved):
+    yref, idx, z = oracle.row_forward(x_np, op)
+    got = y.cpu().numpy().astype(np.float64)
+    if op == "sum":
+        for r in range(x_np.shape[0]):
+            _, a = oracle.exact_sum(x_np[r])
+            assert abs(got[r] - yref[r]) <= 2.0 ** -20 * a, (r, got[r], yref[r])
+    elif op in ("max", "min"):
+        assert np.array_equal(got, yref, equal_nan=True), (got, yref)
+        real = ~np.isnan(yref)
+        assert np.array_equal(np.signbit(got[real]), np.signbit(yref[real]))  # -0 < +0
+        gidx = saved[: 8 * x_np.shape[0]].cpu().view(torch.int64).numpy()
+        assert np.array_equal(gidx, idx)
+    else:
+        for r in range(x_np.shape[0]):
+            ref32 = float(np.float32(yref[r]))  # the float32 output rounds once
+            if ref32 == 0.0 or math.isinf(ref32):
+                assert got[r] == ref32, (r, got[r], yref[r])
+            else:
+                n = x_np.shape[1]
+                bound = (n - 1) * 2.0 ** -53 * 1.001 + 2.0 ** -24
+                assert abs(got[r] - yref[r]) <= bound * abs(yref[r]), (r, got[r], yref[r])
+
+
+def check_backward(x_np, op, g_np, grad):
+    ref = oracle.row_grad(x_np, op, g_np.astype(np.float64))
+    got = grad.cpu().numpy().astype(np.float64)
+    if op in ("sum", "max", "min"):
+        assert np.array_equal(got, ref.astype(np.float32).astype(np.float64))
+    else:
+        assert prod_grad_ok(got, ref), float(np.max(np.abs(got - ref) / (np.abs(ref) + 1e-300)))
+
+
+def run_rows(x_np, op, g_np=None, pad=False):
+    rows, cols = x_np.shape
+    print(f"[rowwise] op={op} shape={x_np.shape} pad={pad}", flush=True)
+    if pad:  # rows not 16-byte aligned: view into a larger buffer
+        big = torch.empty(rows * cols + 1, dtype=torch.float32, device="cuda")
+        x = big[1:].view(rows, cols)
+        x.copy_(torch.from_numpy(x_np))
+    else:
+        x = torch.from_numpy(x_np).cuda()
+    y, saved = rd.rowreduce_forward(x, op)
+    torch.cuda.synchronize()
+    check_forward(x_np, op, y, saved)
+    if g_np is None:
+        g_np = np.linspace(-2.0, 3.0, rows).astype(np.float32)
+    grad = rd.rowreduce_backward(x, torch.from_numpy(g_np).cuda(), saved, op)
+    torch.cuda.synchronize()
+    check_backward(x_np, op, g_np, grad)
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_rowwise_shapes(op, shape):
+    rows, cols = shape
+    rng = np.random.default_rng(rows * 1000 + cols)
+    if op == "prod":
+        x = rng.uniform(0.99, 1.01, size=shape).astype(np.float32)
+    else:
+        x = rng.standard_normal(shape).astype(np.float32)
+    run_rows(x, op)
+    run_rows(x, op, pad=True)
+
+
+@pytest.mark.parametrize("op", ["max", "min"])
+def test_rowwise_ties_lowest_index(op):
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((6, 50_000)).astype(np.float32)
+    ext = np.float32(9.0 if op == "max" else -9.0)
+    x[0, [17, 49_999]] = ext
+    x[1, [40_000, 3, 16_384]] = ext        # lowest index 3, across chunks
+    x[2, :] = ext                         # all equal -> column 0
+    x[3, [16_383, 16_384]] = ext          # chunk boundary
+    x[4, [0, 1]] = ext
+    x[5, 7] = np.float32("nan")           # NaN wins, first NaN
+    x[5, 9] = np.float32("nan")
+    run_rows(x, op)
+
+
+def test_rowwise_signed_zero_extremes():
+    x = np.array([[-0.0, 0.0, -0.0, 0.0], [0.0, -0.0, 0.0, -0.0]], np.float32)
+    run_rows(x, "max")
+    run_rows(x, "min")
+
+
+def test_rowwise_prod_zero_counts():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.95, 1.05, size=(6, 40_000)).astype(np.float32)
+    x[1, 12_345] = 0.0                      # one zero
+    x[2, [5, 39_999]] = 0.0                 # two zeros
+    x[3, 16_384] = 0.0                      # one zero at a chunk start
+    x[4, :] = 0.0                           # all zeros
+    x[5, [0]] = -0.0                        # one negative zero
+    run_rows(x, "prod")
+
+
+@pytest.mark.parametrize("op", ["sum", "max", "prod"])
+def test_rowwise_finite_differences_slice(op):
+    # FP64 central differences of the exact function on a 64 x 1024 slice
+    x = W.rowwise(64, 1024, op, salt=11)
+    g = np.random.default_rng(1).standard_normal(64).astype(np.float32)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    y = rd.rowreduce(xt, op)
+    y.backward(torch.from_numpy(g).cuda())
+    grad = xt.grad.cpu().numpy().astype(np.float64)
+    x64 = x.astype(np.float64)
+    f = {"sum": np.sum, "max": np.max, "prod": np.prod}[op]
+    h = 2.0 ** -12
+    rng = np.random.default_rng(2)
+    checked = 0
+    for r in range(64):
+        cols = rng.choice(1024, size=16, replace=False)
+        if op == "max":
+            cols = np.append(cols, int(np.argmax(x64[r])))
+        for j in cols:
+            if op == "max":
+                others = np.delete(x64[r], j)
+                gap = abs(x64[r, j] - np.max(others))
+                if gap < 2 * h:  # a tie within the step: one-sided slopes differ
+                    continue
+            up, dn = x64[r].copy(), x64[r].copy()
+            up[j] += h
+            dn[j] -= h
+            fd = g[r] * (f(up) - f(dn)) / (2 * h)
+            tol = 2.0 ** -12 * abs(fd) + 1e-6 * abs(g[r]) * (abs(f(x64[r])) if op == "prod" else 1.0)
+            assert abs(grad[r, j] - fd) <= tol, (op, r, j, grad[r, j], fd)
+            checked += 1
+    assert checked > 500
+
+
+def test_rowwise_autograd_matches_kernels():
+    x = W.rowwise(16, 5000, "max", salt=2)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    g = torch.linspace(-1, 1, 16, device="cuda")
+    rd.rowreduce(xt, "max").backward(g)
+    y, saved = rd.rowreduce_forward(torch.from_numpy(x).cuda(), "max")
+    direct = rd.rowreduce_backward(torch.from_numpy(x).cuda(), g, saved, "max")
+    assert torch.equal(xt.grad, direct)
+
+
+def test_rowwise_prod_supplement_no_zero_rows():
+    # rows without zeros take the prefix/suffix-scan path at full width
+    x = W.rowwise(8, 262_144, "prod", salt=7)
+    x[x == 0] = np.float32(1.0)
+    x[5, 1000] = 0.0  # and one row with a single zero
+    run_rows(x, "prod")
+
+
+@pytest.mark.parametrize("op", ["sum", "max", "prod"])
+def test_rowwise_full_shape_sampled_rows(op):
+    rows, cols = 4096, 262_144
+    x_np = W.rowwise(rows, cols, op)
+    x = torch.from_numpy(x_np).cuda()
+    g_np = np.random.default_rng(4).standard_normal(rows).astype(np.float32)
+    y, saved = rd.rowreduce_forward(x, op)
+    grad = rd.rowreduce_backward(x, torch.from_numpy(g_np).cuda(), saved, op)
+    torch.cuda.synchronize()
+    sample = [0, 1, rows - 1] + list(np.random.default_rng(9).choice(rows, 6, replace=False))
+    if op == "max":
+        sample += list(W.tie_rows(rows, cols, op)[:4])
+    sample = sorted(set(int(s) for s in sample))
+    ysub = y[sample]
+    if op in ("max", "min"):
+        full_idx = saved[: 8 * rows].view(torch.int64)
+        sub_saved = full_idx[sample].contiguous().view(torch.uint8)
+    else:
+        sub_saved = None
+    xs = x_np[sample]
+    check_forward(xs, op, ysub, sub_saved if sub_saved is not None else saved)
+    check_backward(xs, op, g_np[sample], grad[sample])
+    del x, grad
+    torch.cuda.empty_cache()
