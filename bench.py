@@ -13,6 +13,9 @@ Also measured (outside the timed headline loop) and reported in the same line:
 * row-wise forward + backward over a 4096 x 262144 float32 matrix for +, max
   and x, time per algorithmic byte relative to the plain kernel's;
 * the compensated sum at 2^28;
+* the precision table: plain and compensated sums of 2^28 bf16/fp16/fp32
+  values (uniform, log-uniform random-sign, +-4^k cancellation) against the
+  exact sum;
 * cpu_baseline: the CPU oracle (exact long-accumulator sum, one thread) on
   the same 2^28 input.
 
@@ -25,6 +28,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -111,6 +116,34 @@ def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
     return res
 
 
+def bench_precision(rd, W, oracle, torch, n):
+    """Error of the float32-accumulated and the compensated sum against the
+    exact sum, for each stored dtype and data set (2^28 elements)."""
+    dev = torch.device("cuda")
+    res = {}
+    for dtype in ("bfloat16", "float16", "float32"):
+        for kind in W.PRECISION_SETS:
+            x_np = W.precision(n, dtype, kind)
+            exact, abs_sum = oracle.exact_sum(x_np, dtype)
+            if dtype == "float32":
+                x = torch.from_numpy(x_np).to(dev)
+            else:
+                x = torch.from_numpy(x_np.view(np.int16)).to(dev).view(
+                    torch.bfloat16 if dtype == "bfloat16" else torch.float16)
+            plain = float(rd.reduce(x, "sum").item())
+            comp = float(rd.reduce_compensated(x).item())
+            ep, ec = abs(plain - exact), abs(comp - exact)
+            res[f"{dtype}/{kind}"] = {
+                "exact": exact, "sum_abs": abs_sum,
+                "plain_err_over_sum_abs": ep / abs_sum, "comp_err_over_sum_abs": ec / abs_sum,
+                "plain_err_over_exact": ep / abs(exact) if exact else None,
+                "comp_err_over_exact": ec / abs(exact) if exact else None,
+                "plain_pass_2^-20": ep <= 2.0 ** -20 * abs_sum, "comp_pass_2^-40": ec <= 2.0 ** -40 * abs_sum}
+            log(f"precision {dtype}/{kind}: plain {ep / abs_sum:.3e}  compensated {ec / abs_sum:.3e}")
+            del x, x_np
+    return res
+
+
 def bench_rowwise(rd, torch, steps, warmup, plain_s_per_byte):
     rows, cols = 4096, 262144
     dev = torch.device("cuda")
@@ -152,6 +185,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-secondary", action="store_true", help="headline kernel only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -159,7 +193,6 @@ def main() -> int:
               "the reduction's multi-GPU form is not part of this library", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1710_07358_amd as rd
@@ -214,6 +247,9 @@ def main() -> int:
                                                  args.warmup, plain_spb)
         log("row-wise forward + backward")
         secondary["rowwise"] = bench_rowwise(rd, torch, max(args.steps // 5, 3), 2, plain_spb)
+        if not args.no_precision:
+            log("precision sets")
+            secondary["precision"] = bench_precision(rd, W, oracle, torch, n)
 
     line = {
         "metric": METRIC,

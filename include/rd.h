@@ -83,8 +83,16 @@ typedef struct rd_config {
                            2 one contiguous run of chunks per work-group */
 } rd_config;
 
-/* Kinds of launch a configuration applies to. */
-typedef enum rd_kind { RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2 } rd_kind;
+/* Kinds of launch a configuration applies to.  For the row-wise forward
+ * (RD_KIND_ROWWISE) and backward (RD_KIND_ROWWISE_BWD) the work-group size is
+ * fixed at 256, `unroll` is the number of 4-column stripes each work-item
+ * handles per step (1, 2, 4 or 8; 16 is treated as 8), `blocks_per_cu` sizes
+ * the persistent grid over rows, and `nontemporal` applies to the forward's
+ * loads and the backward's stores. */
+typedef enum rd_kind {
+    RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2, RD_KIND_ROWWISE = 3,
+    RD_KIND_ROWWISE_BWD = 4
+} rd_kind;
 
 /* ---- library and workspace management ---------------------------------- */
 

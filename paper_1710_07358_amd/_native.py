@@ -12,13 +12,14 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime librd.so links against)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librd.so")
+TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.txt")
 
 # enums of include/rd.h
 RD_I32, RD_U32, RD_F32, RD_F64, RD_F16, RD_BF16 = range(6)
 RD_SUM, RD_PROD, RD_MIN, RD_MAX, RD_AND, RD_OR, RD_XOR = range(7)
 RD_OK, RD_ERR_INVALID_ARG, RD_ERR_UNSUPPORTED, RD_ERR_HIP, RD_ERR_NOMEM, RD_ERR_CAPTURE, RD_ERR_WORKSPACE = (
     0, -1, -2, -3, -4, -5, -6)
-RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED = range(3)
+RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD = range(5)
 
 STATUS_NAMES = {0: "RD_OK", -1: "RD_ERR_INVALID_ARG", -2: "RD_ERR_UNSUPPORTED", -3: "RD_ERR_HIP",
                 -4: "RD_ERR_NOMEM", -5: "RD_ERR_CAPTURE", -6: "RD_ERR_WORKSPACE"}
@@ -74,6 +75,11 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = handle
+        # The measured launch table for gfx950, when present, replaces the
+        # built-in defaults (RD_TUNE_TABLE=<path> picks another, =none keeps them).
+        table = os.environ.get("RD_TUNE_TABLE", TUNED_TABLE)
+        if table != "none" and os.path.exists(table):
+            check(handle.rd_tune_load(table.encode()))
     return _lib
 
 

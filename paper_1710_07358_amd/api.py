@@ -19,7 +19,8 @@ TORCH_DTYPE = {v: k for k, v in DTYPES.items()}
 OPS = {"sum": N.RD_SUM, "prod": N.RD_PROD, "min": N.RD_MIN, "max": N.RD_MAX,
        "and": N.RD_AND, "or": N.RD_OR, "xor": N.RD_XOR}
 KINDS = {"plain": N.RD_KIND_PLAIN, "compensated": N.RD_KIND_COMPENSATED,
-         "segmented": N.RD_KIND_SEGMENTED}
+         "segmented": N.RD_KIND_SEGMENTED, "rowwise": N.RD_KIND_ROWWISE,
+         "rowwise_bwd": N.RD_KIND_ROWWISE_BWD}
 
 
 def _dt(t: torch.Tensor) -> int:

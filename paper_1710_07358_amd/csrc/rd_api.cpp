@@ -172,12 +172,19 @@ std::vector<TuneEntry> builtin_table() {
         t.push_back({kind, es, oc, 18, 23, {256, 4, 2, 0, 1}});
         t.push_back({kind, es, oc, 24, 62, {512, 2, 2, 1, 1}});
       }
+  // Row-wise (float32), measured at 4096 x 262144: the forward streams best
+  // with non-temporal loads; the write-only backward with plain stores.
+  t.push_back({RD_KIND_ROWWISE, 4, 0, 0, 62, {256, 2, 4, 1, 0}});
+  t.push_back({RD_KIND_ROWWISE, 4, 1, 0, 62, {256, 1, 8, 1, 0}});
+  t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 0, 0}});
+  t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 0, 0}});
   return t;
 }
 
 std::vector<TuneEntry> g_table = builtin_table();
-bool g_forced[3] = {false, false, false};
-rd_config g_force_cfg[3];
+constexpr int kKinds = 5;
+bool g_forced[kKinds] = {false, false, false, false, false};
+rd_config g_force_cfg[kKinds];
 
 int log2_ceil(int64_t n) {
   int l = 0;
@@ -208,6 +215,13 @@ rd::Launch plan(const rd_config& c, int64_t nvec, int cus, int cap) {
   int64_t g = std::min<int64_t>((int64_t)c.blocks_per_cu * cus, cap);
   g = std::max<int64_t>(1, std::min(g, chunks));
   return rd::Launch{c.block, (int)g, c.unroll, c.nontemporal != 0, c.layout};
+}
+
+// Row-wise kernels: 256 work-items; grid carries blocks per CU; unroll is
+// the number of stripes per step (1, 2, 4, 8).
+rd::Launch row_launch(rd_kind kind, rd_op op, int64_t rows, int64_t cols) {
+  const rd_config c = choose_config(kind, RD_F32, op, rows * cols);
+  return rd::Launch{256, c.blocks_per_cu, c.unroll > 8 ? 8 : c.unroll, c.nontemporal != 0, c.layout};
 }
 
 bool valid_dtype(rd_dtype dt) { return dt >= RD_I32 && dt <= RD_BF16; }
@@ -402,7 +416,8 @@ rd_status rd_rowreduce_fwd(const void* x, int64_t rows, int64_t cols, rd_dtype d
   int dev;
   DeviceInfo info;
   if ((st = current_device(&dev, &info)) != RD_OK) return st;
-  hipError_t e = rd::rowreduce_fwd((const float*)x, rows, cols, op, (float*)y, saved, info.cus, (hipStream_t)stream);
+  const rd::Launch l = row_launch(RD_KIND_ROWWISE, op, rows, cols);
+  hipError_t e = rd::rowreduce_fwd((const float*)x, rows, cols, op, (float*)y, saved, info.cus, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_fwd launch");
 }
 
@@ -422,20 +437,21 @@ rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int6
   int dev;
   DeviceInfo info;
   if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  const rd::Launch l = row_launch(RD_KIND_ROWWISE_BWD, op, rows, cols);
   hipError_t e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in,
-                                   info.cus, (hipStream_t)stream);
+                                   info.cus, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_bwd launch");
 }
 
 rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_config* cfg) {
-  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED || !valid_dtype(dt) || !valid_op(op))
+  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_ROWWISE_BWD || !valid_dtype(dt) || !valid_op(op))
     return fail(RD_ERR_INVALID_ARG, "rd_config_get: bad argument");
   *cfg = choose_config(kind, dt, op, n);
   return RD_OK;
 }
 
 rd_status rd_config_force(rd_kind kind, const rd_config* cfg) {
-  if (kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
+  if (kind < RD_KIND_PLAIN || kind > RD_KIND_ROWWISE_BWD) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
   if (cfg && !valid_config(*cfg))
     return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d layout %d",
                 cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal, cfg->layout);
@@ -464,7 +480,7 @@ rd_status rd_tune_load(const char* path) {
     int k = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &e.kind, &e.esize, &e.opclass, &e.lo, &e.hi,
                         &e.cfg.block, &e.cfg.unroll, &e.cfg.blocks_per_cu, &e.cfg.nontemporal, &e.cfg.layout);
     if (k <= 0) continue;
-    if (k != 10 || e.kind < 0 || e.kind > 2 || !valid_config(e.cfg)) {
+    if (k != 10 || e.kind < 0 || e.kind >= kKinds || !valid_config(e.cfg)) {
       std::fclose(f);
       return fail(RD_ERR_INVALID_ARG, "rd_tune_load: %s:%d: malformed entry", path, lineno);
     }

@@ -64,11 +64,12 @@ SegFn seg_f32(rd_op op, int unroll, bool nt);
 SegFn seg_f64(rd_op op, int unroll, bool nt);
 SegFn seg_half(rd_dtype dt, rd_op op, int unroll, bool nt);
 
-// Row-wise forward / backward (float32).
+// Row-wise forward / backward (float32).  Launch: grid = work-groups per CU
+// (capped by rows), unroll = stripes per step (1, 2, 4, 8).
 hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, float* y,
-                         void* saved, int cus, hipStream_t s);
+                         void* saved, int cus, const Launch& l, hipStream_t s);
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows,
-                         int64_t cols, rd_op op, float* grad, int cus, hipStream_t s);
+                         int64_t cols, rd_op op, float* grad, int cus, const Launch& l, hipStream_t s);
 size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols);
 
 }  // namespace rd

@@ -53,12 +53,12 @@ __device__ __forceinline__ float key_float(int32_t k) {
 
 // Load the 4 consecutive floats of stripe u at column `col` (missing columns
 // of a ragged chunk take `fill`).  AL: the row pointer and cols keep every
-// stripe 16-byte aligned, so one global_load_dwordx4 serves.
-template <bool AL>
+// stripe 16-byte aligned, so one global_load_dwordx4 serves.  NT: non-temporal.
+template <bool AL, bool NT = true>
 __device__ __forceinline__ void load_stripe(const float* __restrict__ row, int64_t col, int64_t cols,
                                             bool full, float fill, float (&v)[4]) {
   if (AL && (full || col + 3 < cols)) {
-    const u32x4 q = __builtin_nontemporal_load((const u32x4*)(row + col));
+    const u32x4 q = load16<NT>((const u32x4*)(row + col));
 #pragma unroll
     for (int e = 0; e < 4; ++e) v[e] = lane_elem<float>(q, e);
   } else {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void load_stripe(const float* __restrict__ row, int64
   }
 }
 
-template <bool AL>
+template <bool AL, bool NT = true>
 __device__ __forceinline__ void store_stripe(float* __restrict__ row, int64_t col, int64_t cols,
                                              bool full, const float (&v)[4]) {
   if (AL && (full || col + 3 < cols)) {
@@ -77,7 +77,8 @@ __device__ __forceinline__ void store_stripe(float* __restrict__ row, int64_t co
       const uint32_t b = __builtin_bit_cast(uint32_t, v[e]);
       q[e] = b;
     }
-    __builtin_nontemporal_store(q, (u32x4*)(row + col));
+    if constexpr (NT) __builtin_nontemporal_store(q, (u32x4*)(row + col));
+    else *(u32x4*)(row + col) = q;
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -95,13 +96,19 @@ struct ProdAcc {  // chunk-level product state (16 bytes, combinable by DPP)
 
 // ------------------------------------------------------------------ forward
 
-template <Op O, bool AL>
+// Each step covers S stripes of 4 consecutive columns per work-item:
+// kRowBlock * 4 * S columns.  S divides kPerLane / 4, so product chunks are
+// whole numbers of steps.
+template <int S> constexpr int64_t row_step() { return (int64_t)kRowBlock * 4 * S; }
+
+template <Op O, bool AL, int S, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restrict__ x, int64_t rows,
                                                             int64_t cols, float* __restrict__ y,
                                                             void* __restrict__ saved) {
-  constexpr int U = kPerLane / 4;  // stripes of 4 consecutive columns per chunk
+  constexpr int64_t STEP = row_step<S>();
+  static_assert(kChunk % STEP == 0, "a chunk is a whole number of steps");
   const int t = threadIdx.x;
-  const int64_t nch = chunks_of(cols);
+  const int64_t nsteps = (cols + STEP - 1) / STEP;
   __shared__ float lds_f[kRowWaves];
   __shared__ uint64_t lds_u[kRowWaves];
   __shared__ ProdAcc lds_p[kRowWaves];
@@ -109,25 +116,25 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const float* __restrict__ row = x + r * cols;
     if constexpr (O == Op::Sum) {
-      float acc[U][4];
+      float acc[S][4];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < S; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[u][e] = 0.0f;
-      for (int64_t k = 0; k < nch; ++k) {
-        const int64_t c0 = k * kChunk;
-        const bool full = c0 + kChunk <= cols;
+      for (int64_t st = 0; st < nsteps; ++st) {
+        const int64_t c0 = st * STEP;
+        const bool full = c0 + STEP <= cols;
+        float v[S][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float v[4];
-          load_stripe<AL>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 0.0f, v);
+        for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 0.0f, v[u]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[u][e] += v[e];
-        }
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[u][e] += v[u][e];
       }
       float mine = 0.0f;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < S; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) mine += acc[u][e];
       const float tot = block_reduce(mine, 0.0f, [](float a, float b) { return a + b; }, lds_f);
@@ -136,44 +143,51 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
     } else if constexpr (O == Op::Max || O == Op::Min) {
       constexpr bool MAX = (O == Op::Max);
       constexpr int32_t NAN_KEY = MAX ? 0x7FFFFFFF : (int32_t)0x80000000;
-      constexpr int32_t NONE_KEY = MAX ? (int32_t)0x80000000 : 0x7FFFFFFF;  // below/above every value
-      int32_t best[U][4];
-      int32_t at[U][4];  // chunk index where best was first reached
+      const float ident = MAX ? -__builtin_inff() : __builtin_inff();
+      // Per slot: the IEEE 754-2019 maximum (minimum) so far and the step at
+      // which its bits last changed.  Equal values leave the bits alone, so the
+      // first occurrence is kept; once a NaN is in, the slot stops updating.
+      float best[S][4];
+      int32_t at[S][4];
+      for (int64_t st = 0; st < nsteps; ++st) {
+        const int64_t c0 = st * STEP;
+        const bool full = c0 + STEP <= cols;
+        float v[S][4];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+        for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, ident, v[u]);
+        if (st == 0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          best[u][e] = NONE_KEY;
-          at[u][e] = -1;
-        }
-      for (int64_t k = 0; k < nch; ++k) {
-        const int64_t c0 = k * kChunk;
-        const bool full = c0 + kChunk <= cols;
+          for (int u = 0; u < S; ++u)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float v[4];
-          const int64_t col = c0 + ((int64_t)u * kRowBlock + t) * 4;
-          load_stripe<AL>(row, col, cols, full, 0.0f, v);
+            for (int e = 0; e < 4; ++e) {
+              const bool valid = full || (((int64_t)u * kRowBlock + t) * 4 + e < cols);
+              best[u][e] = v[u][e];
+              at[u][e] = valid ? 0 : -1;
+            }
+        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const bool valid = full || (col + e < cols);
-            const int32_t key = float_key(v[e], NAN_KEY);
-            const bool better = valid && (MAX ? key > best[u][e] : key < best[u][e]);
-            best[u][e] = better ? key : best[u][e];
-            at[u][e] = better ? (int32_t)k : at[u][e];
-          }
+          for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float nb = MAX ? __builtin_elementwise_maximum(best[u][e], v[u][e])
+                                   : __builtin_elementwise_minimum(best[u][e], v[u][e]);
+              const bool changed = (__builtin_bit_cast(uint32_t, nb) != __builtin_bit_cast(uint32_t, best[u][e])) &&
+                                   (best[u][e] == best[u][e]);
+              at[u][e] = changed ? (int32_t)st : at[u][e];
+              best[u][e] = nb;
+            }
         }
       }
       // Pack (key, column) so one unsigned max/min picks the extreme and, among
       // equal keys, the lowest column.
       uint64_t mine = MAX ? 0ull : ~0ull;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < S; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if (at[u][e] < 0) continue;
-          const uint32_t col = (uint32_t)((int64_t)at[u][e] * kChunk + ((int64_t)u * kRowBlock + t) * 4 + e);
-          const uint32_t ukey = (uint32_t)best[u][e] ^ 0x80000000u;
+          const uint32_t col = (uint32_t)((int64_t)at[u][e] * STEP + ((int64_t)u * kRowBlock + t) * 4 + e);
+          const uint32_t ukey = (uint32_t)float_key(best[u][e], NAN_KEY) ^ 0x80000000u;
           const uint64_t packed = MAX ? (((uint64_t)ukey << 32) | (uint64_t)(0xFFFFFFFFu - col))
                                       : (((uint64_t)ukey << 32) | (uint64_t)col);
           mine = MAX ? (packed > mine ? packed : mine) : (packed < mine ? packed : mine);
@@ -183,7 +197,7 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
           mine, id, [](uint64_t a, uint64_t b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); }, lds_u);
       if (t == 0) {
         int64_t col = -1;
-        float val = MAX ? -__builtin_inff() : __builtin_inff();
+        float val = ident;
         if (tot != id) {
           const uint32_t lo = (uint32_t)tot;
           col = MAX ? (int64_t)(0xFFFFFFFFu - lo) : (int64_t)lo;
@@ -195,6 +209,7 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       }
       __syncthreads();
     } else {  // product
+      const int64_t nch = chunks_of(cols);
       ProdHeader* hdr = (ProdHeader*)saved;
       float* chunk_prod = (float*)((char*)saved + rows * (int64_t)sizeof(ProdHeader));
       int32_t zeros = 0, first = INT32_MAX;
@@ -203,22 +218,23 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
         return ProdAcc{a.p * b.p, a.zeros + b.zeros, a.first < b.first ? a.first : b.first};
       };
       for (int64_t k = 0; k < nch; ++k) {
-        const int64_t c0 = k * kChunk;
-        const bool full = c0 + kChunk <= cols;
         double p = 1.0;
         int32_t z = 0, fz = INT32_MAX;
+        for (int64_t c0 = k * kChunk; c0 < (k + 1) * kChunk && c0 < cols; c0 += STEP) {
+          const bool full = c0 + STEP <= cols;
+          float v[S][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float v[4];
-          const int64_t col = c0 + ((int64_t)u * kRowBlock + t) * 4;
-          load_stripe<AL>(row, col, cols, full, 1.0f, v);
+          for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 1.0f, v[u]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const bool zero = (v[e] == 0.0f);
-            p = zero ? p : p * (double)v[e];
-            z += zero ? 1 : 0;
-            fz = (zero && fz == INT32_MAX) ? (int32_t)(col + e) : fz;
-          }
+          for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const bool zero = (v[u][e] == 0.0f);
+              p = zero ? p : p * (double)v[u][e];
+              z += zero ? 1 : 0;
+              const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
+              fz = (zero && col < fz) ? col : fz;
+            }
         }
         const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0, INT32_MAX}, comb, lds_p);
         if (t == 0) {
@@ -239,24 +255,100 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 
 // ------------------------------------------------------------------ backward
 
-// sum / max / min / product rows with zeros: write-only fill.
-template <Op O, bool AL>
+// Exclusive products of one zero-free row, chunk by chunk (see the file header).
+template <bool AL>
+__device__ void prod_scan_row(const float* __restrict__ row, const float* __restrict__ chunk_prod,
+                              int64_t cols, float gr, float* __restrict__ out,
+                              float (&lds_tot)[kRowWaves][kPerLane / 4]) {
+  constexpr int U = kPerLane / 4;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t nch = chunks_of(cols);
+  auto mul = [](float a, float b) { return a * b; };
+  for (int64_t k = 0; k < nch; ++k) {
+    const int64_t c0 = k * kChunk;
+    const bool full = c0 + kChunk <= cols;
+    float CP = 1.0f, CS = 1.0f;  // products of the chunks before / after this one
+    for (int64_t j = 0; j < k; ++j) CP *= chunk_prod[j];
+    for (int64_t j = k + 1; j < nch; ++j) CS *= chunk_prod[j];
+
+    float v[U][4], m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      load_stripe<AL>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 1.0f, v[u]);
+      m[u] = (v[u][0] * v[u][1]) * (v[u][2] * v[u][3]);  // product of this work-item's 4 columns
+    }
+    // Across the 64 lanes: exclusive prefix (lanes below) and suffix (lanes above).
+    float E[U], F[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float inc = wave_scan_incl(m[u], 1.0f, mul);
+      E[u] = wave_shift_up(inc, 1.0f);
+      const float rinc = wave_scan_incl(wave_reverse(m[u]), 1.0f, mul);
+      F[u] = wave_reverse(wave_shift_up(rinc, 1.0f));
+      if (lane == 63) lds_tot[wave][u] = inc;  // wavefront product of stripe u
+    }
+    __syncthreads();
+    // Across wavefronts and stripes.
+    float R[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float before = 1.0f, after = 1.0f, all = 1.0f;
+#pragma unroll
+      for (int w2 = 0; w2 < kRowWaves; ++w2) {
+        const float q = lds_tot[w2][u];
+        if (w2 < wave) before *= q;
+        if (w2 > wave) after *= q;
+        all *= q;
+      }
+      E[u] *= before;
+      F[u] *= after;
+      R[u] = all;
+    }
+    float SS[U];  // product of whole stripes after u
+    {
+      float acc = 1.0f;
+#pragma unroll
+      for (int u = U - 1; u >= 0; --u) {
+        SS[u] = acc;
+        acc *= R[u];
+      }
+    }
+    float SP = 1.0f;  // product of whole stripes before u
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float left = gr * CP * SP * E[u];
+      const float right = F[u] * SS[u] * CS;
+      SP *= R[u];
+      const float p01 = v[u][0] * v[u][1], p23 = v[u][2] * v[u][3];
+      float o[4];
+      o[0] = left * (v[u][1] * p23) * right;
+      o[1] = left * (v[u][0] * p23) * right;
+      o[2] = left * (p01 * v[u][3]) * right;
+      o[3] = left * (p01 * v[u][2]) * right;
+      store_stripe<AL>(out, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, o);
+    }
+    __syncthreads();  // lds_tot is rewritten by the next chunk
+  }
+}
+
+// sum / max / min, and product rows with zeros: write-only fill in steps of
+// S stripes; product rows without zeros take prod_scan_row.
+template <Op O, bool AL, int S, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_bwd_kernel(const float* __restrict__ x,
                                                             const float* __restrict__ g,
                                                             const void* __restrict__ saved,
                                                             int64_t rows, int64_t cols,
                                                             float* __restrict__ grad) {
-  constexpr int U = kPerLane / 4;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t nch = chunks_of(cols);
-  __shared__ float lds_tot[kRowWaves][U];
+  constexpr int64_t STEP = row_step<S>();
+  const int t = threadIdx.x;
+  const int64_t nsteps = (cols + STEP - 1) / STEP;
+  __shared__ float lds_tot[kRowWaves][kPerLane / 4];
 
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const float gr = g[r];
     float* __restrict__ out = grad + r * cols;
-    int64_t hot = -1;  // the one column receiving a nonzero value (or -1: every column)
+    int64_t hot = -1;  // the one column receiving hot_val (or -1: every column gets fill)
     float hot_val = 0.0f, fill = 0.0f;
-    bool scan = false;
     if constexpr (O == Op::Sum) {
       fill = gr;
     } else if constexpr (O == Op::Max || O == Op::Min) {
@@ -264,105 +356,28 @@ __global__ __launch_bounds__(kRowBlock) void row_bwd_kernel(const float* __restr
       hot_val = gr;
     } else {
       const ProdHeader h = ((const ProdHeader*)saved)[r];
+      if (h.zeros == 0) {
+        const int64_t nch = chunks_of(cols);
+        const float* cp = (const float*)((const char*)saved + rows * (int64_t)sizeof(ProdHeader)) + r * nch;
+        prod_scan_row<AL>(x + r * cols, cp, cols, gr, out, lds_tot);
+        continue;
+      }
       if (h.zeros == 1) {
         hot = h.first_zero;
         hot_val = gr * h.pnz;
-      } else if (h.zeros == 0) {
-        scan = true;
       }
     }
-
-    if (!scan) {
-      for (int64_t k = 0; k < nch; ++k) {
-        const int64_t c0 = k * kChunk;
-        const bool full = c0 + kChunk <= cols;
+    for (int64_t st = 0; st < nsteps; ++st) {
+      const int64_t c0 = st * STEP;
+      const bool full = c0 + STEP <= cols;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t col = c0 + ((int64_t)u * kRowBlock + t) * 4;
-          float v[4];
+      for (int u = 0; u < S; ++u) {
+        const int64_t col = c0 + ((int64_t)u * kRowBlock + t) * 4;
+        float v[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (col + e == hot) ? hot_val : fill;
-          store_stripe<AL>(out, col, cols, full, v);
-        }
+        for (int e = 0; e < 4; ++e) v[e] = (col + e == hot) ? hot_val : fill;
+        store_stripe<AL, NT>(out, col, cols, full, v);
       }
-      continue;
-    }
-
-    // Product row without zeros: exclusive products, no division.
-    const float* __restrict__ row = x + r * cols;
-    const float* chunk_prod = (const float*)((const char*)saved + rows * (int64_t)sizeof(ProdHeader)) + r * nch;
-    auto mul = [](float a, float b) { return a * b; };
-    for (int64_t k = 0; k < nch; ++k) {
-      const int64_t c0 = k * kChunk;
-      const bool full = c0 + kChunk <= cols;
-      float CP = 1.0f, CS = 1.0f;  // products of the chunks before / after this one
-      for (int64_t j = 0; j < k; ++j) CP *= chunk_prod[j];
-      for (int64_t j = k + 1; j < nch; ++j) CS *= chunk_prod[j];
-
-      float v[U][4], m[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        load_stripe<AL>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 1.0f, v[u]);
-        float p = v[u][0];
-#pragma unroll
-        for (int e = 1; e < 4; ++e) p *= v[u][e];
-        m[u] = p;  // product of this work-item's 4 columns of stripe u
-      }
-      // Across the 64 lanes: exclusive prefix (lanes below) and suffix (lanes above).
-      float E[U], F[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const float inc = wave_scan_incl(m[u], 1.0f, mul);
-        E[u] = wave_shift_up(inc, 1.0f);
-        const float rinc = wave_scan_incl(wave_reverse(m[u]), 1.0f, mul);
-        F[u] = wave_reverse(wave_shift_up(rinc, 1.0f));
-        if (lane == 63) lds_tot[wave][u] = inc;  // wavefront product of stripe u
-      }
-      __syncthreads();
-      // Across wavefronts and stripes.
-      float SP = 1.0f;  // product of whole stripes before u
-      float R[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        float before = 1.0f, after = 1.0f, all = 1.0f;
-#pragma unroll
-        for (int w2 = 0; w2 < kRowWaves; ++w2) {
-          const float q = lds_tot[w2][u];
-          if (w2 < wave) before *= q;
-          if (w2 > wave) after *= q;
-          all *= q;
-        }
-        E[u] *= before;
-        F[u] *= after;
-        R[u] = all;
-      }
-      float SS[U];  // product of whole stripes after u
-      {
-        float acc = 1.0f;
-#pragma unroll
-        for (int u = U - 1; u >= 0; --u) {
-          SS[u] = acc;
-          acc *= R[u];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const float left = gr * CP * SP * E[u];
-        const float right = F[u] * SS[u] * CS;
-        SP *= R[u];
-        float o[4];
-        float pre = 1.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float suf = 1.0f;
-#pragma unroll
-          for (int e2 = e + 1; e2 < 4; ++e2) suf *= v[u][e2];
-          o[e] = left * pre * suf * right;
-          pre *= v[u][e];
-        }
-        store_stripe<AL>(out, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, o);
-      }
-      __syncthreads();  // lds_tot is rewritten by the next chunk
     }
   }
 }
@@ -380,49 +395,89 @@ size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
 }
 
 namespace {
-// Persistent grid over rows: at most 8 work-groups per CU.
-int row_grid(int64_t rows, int cus) {
-  const int64_t g = (int64_t)cus * 8;
+// Persistent grid over rows: blocks_per_cu work-groups per CU.
+int row_grid(int64_t rows, int cus, int bpc) {
+  const int64_t g = (int64_t)cus * bpc;
   return (int)(rows < g ? rows : g);
 }
 
-template <Op O, bool AL>
-hipError_t fwd_launch(const float* x, int64_t rows, int64_t cols, float* y, void* saved, int cus,
+template <Op O, bool AL, int S>
+hipError_t fwd_launch(const float* x, int64_t rows, int64_t cols, float* y, void* saved, int grid, bool nt,
                       hipStream_t s) {
-  hipLaunchKernelGGL((row_fwd_kernel<O, AL>), dim3(row_grid(rows, cus)), dim3(kRowBlock), 0, s, x, rows,
-                     cols, y, saved);
+  if (nt) hipLaunchKernelGGL((row_fwd_kernel<O, AL, S, true>), dim3(grid), dim3(kRowBlock), 0, s, x, rows, cols, y, saved);
+  else hipLaunchKernelGGL((row_fwd_kernel<O, AL, S, false>), dim3(grid), dim3(kRowBlock), 0, s, x, rows, cols, y, saved);
+  return hipGetLastError();
+}
+
+template <Op O, bool AL, int S>
+hipError_t bwd_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, float* grad,
+                      int grid, bool nt, hipStream_t s) {
+  if (nt) hipLaunchKernelGGL((row_bwd_kernel<O, AL, S, true>), dim3(grid), dim3(kRowBlock), 0, s, x, g, saved, rows, cols, grad);
+  else hipLaunchKernelGGL((row_bwd_kernel<O, AL, S, false>), dim3(grid), dim3(kRowBlock), 0, s, x, g, saved, rows, cols, grad);
   return hipGetLastError();
 }
 
 template <Op O, bool AL>
-hipError_t bwd_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                      float* grad, int cus, hipStream_t s) {
-  hipLaunchKernelGGL((row_bwd_kernel<O, AL>), dim3(row_grid(rows, cus)), dim3(kRowBlock), 0, s, x, g,
-                     saved, rows, cols, grad);
-  return hipGetLastError();
+hipError_t fwd_s(int S, const float* x, int64_t rows, int64_t cols, float* y, void* saved, int grid, bool nt,
+                 hipStream_t s) {
+  switch (S) {
+    case 1: return fwd_launch<O, AL, 1>(x, rows, cols, y, saved, grid, nt, s);
+    case 2: return fwd_launch<O, AL, 2>(x, rows, cols, y, saved, grid, nt, s);
+    case 4: return fwd_launch<O, AL, 4>(x, rows, cols, y, saved, grid, nt, s);
+    case 8: return fwd_launch<O, AL, 8>(x, rows, cols, y, saved, grid, nt, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <Op O, bool AL>
+hipError_t bwd_s(int S, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, float* grad,
+                 int grid, bool nt, hipStream_t s) {
+  switch (S) {
+    case 1: return bwd_launch<O, AL, 1>(x, g, saved, rows, cols, grad, grid, nt, s);
+    case 2: return bwd_launch<O, AL, 2>(x, g, saved, rows, cols, grad, grid, nt, s);
+    case 4: return bwd_launch<O, AL, 4>(x, g, saved, rows, cols, grad, grid, nt, s);
+    case 8: return bwd_launch<O, AL, 8>(x, g, saved, rows, cols, grad, grid, nt, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <Op O>
+hipError_t fwd_op(bool al, int S, const float* x, int64_t rows, int64_t cols, float* y, void* saved, int grid,
+                  bool nt, hipStream_t s) {
+  return al ? fwd_s<O, true>(S, x, rows, cols, y, saved, grid, nt, s)
+            : fwd_s<O, false>(S, x, rows, cols, y, saved, grid, nt, s);
+}
+
+template <Op O>
+hipError_t bwd_op(bool al, int S, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
+                  float* grad, int grid, bool nt, hipStream_t s) {
+  return al ? bwd_s<O, true>(S, x, g, saved, rows, cols, grad, grid, nt, s)
+            : bwd_s<O, false>(S, x, g, saved, rows, cols, grad, grid, nt, s);
 }
 }  // namespace
 
-hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, float* y, void* saved,
-                         int cus, hipStream_t s) {
-  const bool v4 = (cols % 4 == 0) && ((uintptr_t)x % 16 == 0);
+hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, float* y, void* saved, int cus,
+                         const Launch& l, hipStream_t s) {
+  const bool al = (cols % 4 == 0) && ((uintptr_t)x % 16 == 0);
+  const int grid = row_grid(rows, cus, l.grid);
   switch (op) {
-    case RD_SUM: return v4 ? fwd_launch<Op::Sum, true>(x, rows, cols, y, saved, cus, s) : fwd_launch<Op::Sum, false>(x, rows, cols, y, saved, cus, s);
-    case RD_MAX: return v4 ? fwd_launch<Op::Max, true>(x, rows, cols, y, saved, cus, s) : fwd_launch<Op::Max, false>(x, rows, cols, y, saved, cus, s);
-    case RD_MIN: return v4 ? fwd_launch<Op::Min, true>(x, rows, cols, y, saved, cus, s) : fwd_launch<Op::Min, false>(x, rows, cols, y, saved, cus, s);
-    case RD_PROD: return v4 ? fwd_launch<Op::Prod, true>(x, rows, cols, y, saved, cus, s) : fwd_launch<Op::Prod, false>(x, rows, cols, y, saved, cus, s);
+    case RD_SUM: return fwd_op<Op::Sum>(al, l.unroll, x, rows, cols, y, saved, grid, l.nontemporal, s);
+    case RD_MAX: return fwd_op<Op::Max>(al, l.unroll, x, rows, cols, y, saved, grid, l.nontemporal, s);
+    case RD_MIN: return fwd_op<Op::Min>(al, l.unroll, x, rows, cols, y, saved, grid, l.nontemporal, s);
+    case RD_PROD: return fwd_op<Op::Prod>(al, l.unroll, x, rows, cols, y, saved, grid, l.nontemporal, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                         rd_op op, float* grad, int cus, hipStream_t s) {
-  const bool v4 = (cols % 4 == 0) && ((uintptr_t)grad % 16 == 0) && (op != RD_PROD || (uintptr_t)x % 16 == 0);
+hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, rd_op op,
+                         float* grad, int cus, const Launch& l, hipStream_t s) {
+  const bool al = (cols % 4 == 0) && ((uintptr_t)grad % 16 == 0) && (op != RD_PROD || (uintptr_t)x % 16 == 0);
+  const int grid = row_grid(rows, cus, l.grid);
   switch (op) {
-    case RD_SUM: return v4 ? bwd_launch<Op::Sum, true>(x, g, saved, rows, cols, grad, cus, s) : bwd_launch<Op::Sum, false>(x, g, saved, rows, cols, grad, cus, s);
-    case RD_MAX: return v4 ? bwd_launch<Op::Max, true>(x, g, saved, rows, cols, grad, cus, s) : bwd_launch<Op::Max, false>(x, g, saved, rows, cols, grad, cus, s);
-    case RD_MIN: return v4 ? bwd_launch<Op::Min, true>(x, g, saved, rows, cols, grad, cus, s) : bwd_launch<Op::Min, false>(x, g, saved, rows, cols, grad, cus, s);
-    case RD_PROD: return v4 ? bwd_launch<Op::Prod, true>(x, g, saved, rows, cols, grad, cus, s) : bwd_launch<Op::Prod, false>(x, g, saved, rows, cols, grad, cus, s);
+    case RD_SUM: return bwd_op<Op::Sum>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
+    case RD_MAX: return bwd_op<Op::Max>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
+    case RD_MIN: return bwd_op<Op::Min>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
+    case RD_PROD: return bwd_op<Op::Prod>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,179 @@
+"""Autotuner for the launch table of librd (block, unroll, blocks per CU,
+non-temporal loads, chunk order), per (kind, element size, op class, size
+bucket), plus the unroll sweep that mirrors Section 4's execution-time table.
+
+Each candidate is forced through ``rd_config_force`` and timed with HIP
+events on the launching stream (median of repeated timed batches).  The
+search is coordinate descent from the built-in default: one parameter at a
+time over its allowed values, keeping the fastest, for two passes.
+
+Usage (on a GPU):
+    python -m paper_1710_07358_amd.tune --out paper_1710_07358_amd/tuned_gfx950.txt
+    python -m paper_1710_07358_amd.tune --unroll-sweep
+"""
+from __future__ import annotations
+
+import argparse
+import statistics
+import sys
+import time
+
+import torch
+
+from . import api as rd
+
+# representative size per log2(n) bucket of the built-in table
+BUCKETS = [(0, 17, 1 << 16), (18, 23, 1 << 22), (24, 62, 1 << 28)]
+DTYPE_OF_SIZE = {2: torch.bfloat16, 4: torch.float32, 8: torch.float64}
+OPS_OF_CLASS = {0: "sum", 1: "max", 2: "xor"}
+SPACE = {
+    "plain": {"block": [256, 512, 1024], "unroll": [1, 2, 4, 8, 16], "blocks_per_cu": [1, 2, 4, 8],
+              "nontemporal": [0, 1], "layout": [0, 1, 2]},
+    "compensated": {"block": [256, 512, 1024], "unroll": [1, 2, 4, 8, 16], "blocks_per_cu": [1, 2, 4],
+                    "nontemporal": [0, 1], "layout": [0, 1, 2]},
+    "segmented": {"block": [256, 512, 1024], "unroll": [2, 4, 8], "blocks_per_cu": [1, 2, 4, 8],
+                  "nontemporal": [0, 1], "layout": [0]},
+    "rowwise": {"block": [256], "unroll": [1, 2, 4, 8], "blocks_per_cu": [1, 2, 4, 8],
+                "nontemporal": [0, 1], "layout": [0]},
+    "rowwise_bwd": {"block": [256], "unroll": [1, 2, 4, 8], "blocks_per_cu": [1, 2, 4, 8],
+                    "nontemporal": [0, 1], "layout": [0]},
+}
+KIND_ID = {"plain": 0, "compensated": 1, "segmented": 2, "rowwise": 3, "rowwise_bwd": 4}
+
+
+def time_call(fn, reps: int = 20, batches: int = 3, warm_s: float = 0.05) -> float:
+    """Median seconds per call over `batches` timed batches of `reps` calls."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(batches):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b) / 1e3 / reps)
+    return statistics.median(out)
+
+
+def _valid(kind: str, cfg: dict) -> bool:
+    return cfg["block"] * cfg["blocks_per_cu"] <= 4096
+
+
+def descend(kind: str, start: dict, run, passes: int = 2, log=None) -> tuple[dict, float]:
+    """Coordinate descent over SPACE[kind] from `start`; run() times the forced call."""
+    best = dict(start)
+    rd.config_force(kind, best)
+    best_t = time_call(run)
+    for _ in range(passes):
+        for key, values in SPACE[kind].items():
+            for v in values:
+                if v == best[key]:
+                    continue
+                cand = dict(best, **{key: v})
+                if not _valid(kind, cand):
+                    continue
+                rd.config_force(kind, cand)
+                t = time_call(run)
+                if log:
+                    log(f"  {kind} {cand} {t * 1e6:.1f} us")
+                if t < best_t:
+                    best, best_t = cand, t
+    rd.config_force(kind, None)
+    return best, best_t
+
+
+def _case_runner(kind: str, esize: int, opclass: int, n: int, dev):
+    dtype = DTYPE_OF_SIZE[esize]
+    op = OPS_OF_CLASS[opclass]
+    if kind == "plain":
+        if dtype.is_floating_point:
+            x = torch.rand(n, device=dev).to(dtype)
+        else:
+            x = torch.randint(-1000, 1000, (n,), device=dev, dtype=dtype)
+        out = torch.empty((), dtype=rd.out_dtype(dtype, op), device=dev)
+        return (lambda: rd.reduce(x, op, out=out)), n * esize
+    if kind == "compensated":
+        x = torch.rand(n, device=dev).to(dtype)
+        out = torch.empty((), dtype=torch.float64, device=dev)
+        return (lambda: rd.reduce_compensated(x, out=out)), n * esize
+    raise ValueError(kind)
+
+
+def tune_table(kinds, esizes, log) -> list[str]:
+    dev = torch.device("cuda", torch.cuda.current_device())
+    lines = ["# kind esize opclass log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout"]
+    for kind in kinds:
+        for esize in esizes:
+            if kind == "compensated" and esize == 8:
+                continue
+            for opclass in (0, 1, 2):
+                if kind == "compensated" and opclass != 0:
+                    continue
+                if esize == 2 and opclass == 2:
+                    continue  # 16-bit bitwise: keep defaults
+                for lo, hi, n in BUCKETS:
+                    run, nbytes = _case_runner(kind, esize, opclass, n, dev)
+                    start = rd.config_get(kind, DTYPE_OF_SIZE[esize], OPS_OF_CLASS[opclass], n)
+                    best, t = descend(kind, start, run)
+                    log(f"{kind} esize={esize} opclass={opclass} n=2^{n.bit_length() - 1}: {best} "
+                        f"{t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
+                    lines.append(f"{KIND_ID[kind]} {esize} {opclass} {lo} {hi} {best['block']} {best['unroll']} "
+                                 f"{best['blocks_per_cu']} {best['nontemporal']} {best['layout']}")
+                    del run
+                    torch.cuda.empty_cache()
+    return lines
+
+
+def unroll_sweep(n: int, log) -> list[dict]:
+    """Time the plain float32 sum for U = 1, 2, 4, 8, 16 with the rest of the
+    tuned configuration fixed (the MI355X analogue of Section 4's table)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    x = torch.rand(n, device=dev) * 2 - 1
+    out = torch.empty((), device=dev)
+    base = rd.config_get("plain", torch.float32, "sum", n)
+    rows = []
+    for u in (1, 2, 4, 8, 16):
+        rd.config_force("plain", dict(base, unroll=u))
+        t = time_call(lambda: rd.reduce(x, "sum", out=out), reps=50)
+        rows.append({"unroll": u, "ms": t * 1e3, "GBps": 4 * n / t / 1e9})
+    rd.config_force("plain", None)
+    t1 = rows[0]["ms"]
+    for r in rows:
+        r["speedup"] = t1 / r["ms"]
+        r["usage_pct"] = 100 * r["GBps"] / 8000.0
+        log(f"U={r['unroll']:2d}  {r['ms']:.5f} ms  {r['speedup']:.3f}x  {r['GBps']:.1f} GB/s  {r['usage_pct']:.2f}%")
+    return rows
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None, help="write the tuned table here")
+    ap.add_argument("--kinds", default="plain,compensated")
+    ap.add_argument("--esizes", default="2,4,8")
+    ap.add_argument("--unroll-sweep", action="store_true")
+    args = ap.parse_args()
+
+    def log(msg):
+        print(msg, flush=True)
+
+    if args.unroll_sweep:
+        for n in (5_533_214, 1 << 28):
+            log(f"unroll sweep, float32 sum, n={n}")
+            unroll_sweep(n, log)
+        return 0
+    lines = tune_table(args.kinds.split(","), [int(e) for e in args.esizes.split(",")], log)
+    text = "\n".join(lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    else:
+        sys.stdout.write(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
