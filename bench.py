@@ -178,6 +178,77 @@ def bench_rowwise(rd, torch, steps, warmup, plain_s_per_byte):
     return res
 
 
+# ---------------------------------------------------------------- HBM traffic
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_reduce_kernel_f32_sum_2p28.txt")
+KERNEL_SOURCES = ["paper_1710_07358_amd/csrc/rd_device.hpp", "paper_1710_07358_amd/csrc/reduce_plain.hpp",
+                  "paper_1710_07358_amd/csrc/rd_internal.hpp", "paper_1710_07358_amd/csrc/k_f32_plain.hip"]
+
+
+def kernel_fingerprint(launch: dict) -> str:
+    """Hash of the headline kernel's sources and launch shape: counters taken
+    for another version of either do not describe this one."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    h.update(json.dumps(launch, sort_keys=True).encode())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(launch: dict):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it was taken for a different kernel build or launch shape."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("fingerprint", "").strip() != kernel_fingerprint(launch):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def _pmc_rows(directory: str):
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {directory}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, calib_bytes: int) -> str:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per launch of the reduce kernel, each counter
+    scaled by what it reads for a device copy of calib_bytes."""
+    def per_kernel(rows, counter):
+        sums = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            key = "reduce" if "reduce_kernel" in r["Kernel_Name"] else (
+                "copy" if ("copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"]) else None)
+            if key:
+                sums.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: sorted(v)[len(v) // 2] for k, v in sums.items()}  # median per dispatch
+
+    fetch = per_kernel(_pmc_rows(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_pmc_rows(write_dir), "WRITE_SIZE")
+    kib = calib_bytes / 1024.0
+    s_fetch = kib / fetch["copy"]
+    s_write = kib / write["copy"]
+    reduce_bytes = (fetch["reduce"] * s_fetch + write["reduce"] * s_write) * 1024.0
+    return (f"reduce_fetch_kib {fetch['reduce']:.1f}\nreduce_write_kib {write['reduce']:.1f}\n"
+            f"copy_fetch_kib {fetch['copy']:.1f}\ncopy_write_kib {write['copy']:.1f}\n"
+            f"calibration_copy_bytes {calib_bytes}\nscale_fetch {s_fetch:.5f}\nscale_write {s_write:.5f}\n"
+            f"hbm_bytes_per_launch {reduce_bytes:.0f}\nalgorithmic_bytes_per_launch {4 * 2 ** 28}\n")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,7 +257,20 @@ def main() -> int:
     ap.add_argument("--no-secondary", action="store_true", help="headline kernel only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of the 1 GiB input (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the HBM-traffic summary of two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        import torch  # noqa: F401  (binding import needs it)
+
+        import paper_1710_07358_amd as rd
+
+        launch = rd.config_get("plain", torch.float32, "sum", 2 ** 28)
+        sys.stdout.write(summarize_pmc(*args.summarize_pmc, calib_bytes=4 * 2 ** 28))
+        print(f"fingerprint {kernel_fingerprint(launch)}")
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
@@ -211,6 +295,11 @@ def main() -> int:
     nbytes = 4 * n
     achieved = gbps(nbytes, t)
     got = float(out.item())
+    if args.calibrate_copy:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del y
 
     import oracle  # CPU oracle: correctness check and the cpu_baseline leg
 
@@ -269,7 +358,7 @@ def main() -> int:
                    "launch": cfg},
         "pct_hbm_peak": round(100.0 * achieved / HBM_PEAK_GBPS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": read_traffic(cfg),
                      "kernel": "reduce_kernel<F32 sum>", "bytes_per_launch": nbytes,
                      "avg_launch_ms": round(t * 1e3, 5)},
         "cpu_baseline": cpu,

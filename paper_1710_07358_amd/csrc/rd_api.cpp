@@ -165,13 +165,16 @@ std::vector<TuneEntry> builtin_table() {
   // resident wavefronts per CU stream best; non-temporal loads and XCD-grouped
   // chunks for inputs far beyond the 256 MB MALL.
   std::vector<TuneEntry> t;
-  for (int kind = 0; kind < 3; ++kind)
-    for (int es : {2, 4, 8})
-      for (int oc = 0; oc < 3; ++oc) {
-        t.push_back({kind, es, oc, 0, 17, {256, 2, 4, 0, 0}});
-        t.push_back({kind, es, oc, 18, 23, {256, 4, 2, 0, 1}});
-        t.push_back({kind, es, oc, 24, 62, {512, 2, 2, 1, 1}});
-      }
+  for (int es : {2, 4, 8})
+    for (int oc = 0; oc < 3; ++oc) {
+      t.push_back({RD_KIND_PLAIN, es, oc, 0, 17, {256, 2, 4, 0, 0}});
+      t.push_back({RD_KIND_PLAIN, es, oc, 18, 23, {256, 4, 2, 0, 1}});
+      t.push_back({RD_KIND_PLAIN, es, oc, 24, 62, {512, 2, 2, 1, 1}});
+      t.push_back({RD_KIND_COMPENSATED, es, oc, 0, 17, {256, 2, 4, 0, 0}});
+      t.push_back({RD_KIND_COMPENSATED, es, oc, 18, 23, {256, 4, 2, 0, 1}});
+      t.push_back({RD_KIND_COMPENSATED, es, oc, 24, 62, {256, 8, 1, 1, 1}});
+      t.push_back({RD_KIND_SEGMENTED, es, oc, 0, 62, {1024, 2, 1, 1, 0}});
+    }
   // Row-wise (float32), measured at 4096 x 262144: the forward streams best
   // with non-temporal loads; the write-only backward with plain stores.
   t.push_back({RD_KIND_ROWWISE, 4, 0, 0, 62, {256, 2, 4, 1, 0}});

@@ -89,6 +89,23 @@ def descend(kind: str, start: dict, run, passes: int = 2, log=None) -> tuple[dic
 def _case_runner(kind: str, esize: int, opclass: int, n: int, dev):
     dtype = DTYPE_OF_SIZE[esize]
     op = OPS_OF_CLASS[opclass]
+    if kind == "segmented":
+        from . import workloads as W
+        off = W.offsets_from_lengths(W.segment_lengths())
+        total, nseg = int(off[-1]), len(off) - 1
+        x = (torch.rand(total, device=dev) * 2 - 1).to(dtype)
+        offs = torch.from_numpy(off).to(dev)
+        out = torch.empty(nseg, dtype=rd.out_dtype(dtype, op), device=dev)
+        return (lambda: rd.segmented(x, offs, op, out=out)), total * esize
+    if kind in ("rowwise", "rowwise_bwd"):
+        rows, cols = 4096, 262144
+        rop = {0: "sum", 1: "max"}[opclass]
+        x = torch.randn(rows, cols, device=dev)
+        if kind == "rowwise":
+            return (lambda: rd.rowreduce_forward(x, rop)), rows * cols * 4
+        g = torch.randn(rows, device=dev)
+        _, saved = rd.rowreduce_forward(x, rop)
+        return (lambda: rd.rowreduce_backward(x, g, saved, rop)), rows * cols * 4
     if kind == "plain":
         if dtype.is_floating_point:
             x = torch.rand(n, device=dev).to(dtype)
@@ -107,17 +124,25 @@ def tune_table(kinds, esizes, log) -> list[str]:
     dev = torch.device("cuda", torch.cuda.current_device())
     lines = ["# kind esize opclass log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout"]
     for kind in kinds:
+        row_kind = kind in ("rowwise", "rowwise_bwd")
         for esize in esizes:
             if kind == "compensated" and esize == 8:
                 continue
+            if row_kind and esize != 4:
+                continue  # row-wise kernels are float32 only
             for opclass in (0, 1, 2):
                 if kind == "compensated" and opclass != 0:
                     continue
+                if row_kind and opclass == 2:
+                    continue
                 if esize == 2 and opclass == 2:
                     continue  # 16-bit bitwise: keep defaults
-                for lo, hi, n in BUCKETS:
+                # the segmented and row-wise launches are planned for one size bucket
+                buckets = [(0, 62, 1 << 28)] if kind in ("segmented", "rowwise", "rowwise_bwd") else BUCKETS
+                for lo, hi, n in buckets:
                     run, nbytes = _case_runner(kind, esize, opclass, n, dev)
                     start = rd.config_get(kind, DTYPE_OF_SIZE[esize], OPS_OF_CLASS[opclass], n)
+                    start["block"] = 256 if row_kind else start["block"]
                     best, t = descend(kind, start, run)
                     log(f"{kind} esize={esize} opclass={opclass} n=2^{n.bit_length() - 1}: {best} "
                         f"{t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
@@ -152,7 +177,7 @@ def unroll_sweep(n: int, log) -> list[dict]:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None, help="write the tuned table here")
-    ap.add_argument("--kinds", default="plain,compensated")
+    ap.add_argument("--kinds", default="plain,compensated,segmented,rowwise,rowwise_bwd")
     ap.add_argument("--esizes", default="2,4,8")
     ap.add_argument("--unroll-sweep", action="store_true")
     args = ap.parse_args()
