@@ -105,7 +105,40 @@ def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
             else:
                 assert got[sidx] == oracle.reduce(seg, "max", "float32"), sidx
         t = min(eager, replay)
+        per_seg = None
+        if op == "sum":
+            # baseline: one plain launch per segment (65,536 launches), eager and graph-captured
+            outs = torch.empty(nseg, dtype=torch.float32, device=dev)
+            views = [x[int(off[i]):int(off[i + 1])] for i in range(nseg)]
+
+            def one_per_segment():
+                for i in range(nseg):
+                    rd.reduce(views[i], "sum", out=outs[i], workspace=ws)
+
+            one_per_segment()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one_per_segment()
+            torch.cuda.synchronize()
+            t_loop = time.perf_counter() - t0
+            g2 = torch.cuda.CUDAGraph()
+            s2 = torch.cuda.Stream()
+            s2.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s2):
+                with torch.cuda.graph(g2, stream=s2):
+                    one_per_segment()
+            torch.cuda.current_stream().wait_stream(s2)
+            t_g2 = time_launches(g2.replay, 3, 1, torch)
+            got_ps = outs.cpu().numpy().astype(np.float64)
+            for sidx in sample:  # the baseline must be right too
+                ref, asum = oracle.exact_sum(x_np[int(off[sidx]):int(off[sidx + 1])])
+                assert abs(got_ps[sidx] - ref) <= 2.0 ** -20 * asum, sidx
+            per_seg = {"launches": nseg, "ms_eager_host_loop": round(t_loop * 1e3, 2),
+                       "ms_graph_replay": round(t_g2 * 1e3, 3),
+                       "single_launch_speedup_vs_graph": round(t_g2 / t, 1)}
+            del g2
         res[op] = {"ms": round(t * 1e3, 4), "ms_eager": round(eager * 1e3, 4), "ms_graph": round(replay * 1e3, 4),
+                   "one_launch_per_segment": per_seg,
                    "GBps": round(gbps(algo_bytes, t), 1),
                    "per_byte_vs_plain": round((t / algo_bytes) / plain_s_per_byte, 4),
                    "checked_segments": int(len(sample)),

@@ -139,6 +139,20 @@ rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
 rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out,
                                 rd_workspace* ws, void* stream);
 
+/* The two designs the paper describes, kept as measured baselines (sum of
+ * int32, wrapping, or float32; out: device pointer to one element):
+ *   variant 0: the two-stage reduction of Section 2.3 -- as many work-items as
+ *              the device keeps resident, one scalar load per step, a halving
+ *              LDS tree with a barrier per level, a second launch for the
+ *              partials (unroll must be 1);
+ *   variant 1: the new approach of Section 3 -- the global loop unrolled F =
+ *              `unroll` times (1..8 or 16) with the algebraic bounds guard and
+ *              the barrier-free LDS tree, on one-wavefront work-groups (the
+ *              only size at which that tree is race-free), then stage 2.
+ * Two launches; not deterministic across unroll values for float32. */
+rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int variant, int unroll,
+                                 void* out, rd_workspace* ws, void* stream);
+
 /* ---- segmented reduction ------------------------------------------------- */
 
 /* out[s] = x[offsets[s]] (+) ... (+) x[offsets[s+1]-1] for s in [0, nseg),

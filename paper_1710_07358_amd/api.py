@@ -120,6 +120,19 @@ def reduce_compensated(x: torch.Tensor, out: torch.Tensor | None = None,
     return out
 
 
+def reduce_paper_design(x: torch.Tensor, variant: int, unroll: int = 1, out: torch.Tensor | None = None,
+                        workspace: Workspace | None = None) -> torch.Tensor:
+    """Sum by one of the paper's own designs (variant 0: two-stage; 1: unrolled
+    F times with the barrier-free tree), int32 or float32, for comparison."""
+    x = _dev_tensor(x, "x")
+    if out is None:
+        out = torch.empty((), dtype=x.dtype, device=x.device)
+    with torch.cuda.device(x.device):
+        N.check(N.lib().rd_reduce_paper_design(x.data_ptr() if x.numel() else None, x.numel(), _dt(x), int(variant),
+                                               int(unroll), out.data_ptr(), _ws(workspace), _stream(x.device)))
+    return out
+
+
 def segmented(x: torch.Tensor, offsets: torch.Tensor, op: str, out: torch.Tensor | None = None,
               workspace: Workspace | None = None) -> torch.Tensor:
     """out[s] = reduce(x[offsets[s]:offsets[s+1]], op) for every segment, one launch."""

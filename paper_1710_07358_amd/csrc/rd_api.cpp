@@ -80,7 +80,7 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t counters_bytes() { return round_up(kAlign + (size_t)rd::kMaxSegWaves * 4, kAlign); }
 size_t partial_bytes() { return round_up((size_t)rd::kMaxGrid * rd::kPartialWords * 8, kAlign); }
 size_t carry_bytes() { return round_up((size_t)rd::kMaxSegWaves * 2 * rd::kCarryWords * 8, kAlign); }
-size_t workspace_bytes() { return counters_bytes() + partial_bytes() + carry_bytes(); }
+size_t workspace_bytes() { return counters_bytes() + partial_bytes() + carry_bytes() + (size_t)rd::kDesignBytes; }
 
 rd_status create_workspace(rd_workspace** out, int device) {
   int prev = -1;
@@ -110,6 +110,8 @@ rd_status create_workspace(rd_workspace** out, int device) {
   p += partial_bytes();
   s.carry = (uint64_t*)p;
   s.carry_cap = (int64_t)rd::kMaxSegWaves * 2;
+  p += carry_bytes();
+  s.design = p;
   *out = ws;
   return RD_OK;
 }
@@ -397,6 +399,28 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
   const rd::Launch l{cfg.block, grid, cfg.unroll, cfg.nontemporal != 0, cfg.layout};
   hipError_t e = fn(x, offsets, nseg, out, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_segmented_reduce launch");
+}
+
+rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int variant, int unroll, void* out,
+                                 rd_workspace* ws, void* stream) {
+  if (dt != RD_F32 && dt != RD_I32)
+    return fail(RD_ERR_UNSUPPORTED, "rd_reduce_paper_design: int32 or float32 only");
+  if (variant != 0 && variant != 1) return fail(RD_ERR_INVALID_ARG, "rd_reduce_paper_design: variant 0 or 1");
+  const bool f_ok = unroll >= 1 && (unroll <= 8 || unroll == 16);
+  if ((variant == 0 && unroll != 1) || !f_ok)
+    return fail(RD_ERR_INVALID_ARG, "rd_reduce_paper_design: unroll %d (variant 0: 1; variant 1: 1..8 or 16)", unroll);
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "rd_reduce_paper_design: n < 0");
+  rd_status st;
+  if (n > 0 && (st = check_ptr(x, 4, "x")) != RD_OK) return st;
+  if ((st = check_ptr(out, 4, "out")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  hipError_t e = rd::paper_design_reduce(n > 0 ? x : out, n, dt, variant, unroll, out, w->scratch.design,
+                                         (int)(rd::kDesignBytes / 4), info.cus, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce_paper_design launch");
 }
 
 size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols) {

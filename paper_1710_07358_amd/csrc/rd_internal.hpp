@@ -29,7 +29,10 @@ struct Scratch {
   uint64_t* carry;      // segmented: kCarryWords words per slot, 2 slots per wavefront
   int64_t partial_cap;  // work-groups
   int64_t carry_cap;    // carry slots
+  void* design;         // paper-design baselines: plain partials (kDesignBytes)
 };
+
+constexpr int64_t kDesignBytes = 256 * 1024;
 
 constexpr int kPartialWords = 4;  // up to 16-byte partials (double-double)
 constexpr int kCarryWords = 2;    // up to 8-byte accumulators
@@ -71,5 +74,11 @@ hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, f
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows,
                          int64_t cols, rd_op op, float* grad, int cus, const Launch& l, hipStream_t s);
 size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols);
+
+// The paper's two designs (sum of int32 / float32), for comparison:
+// variant 0 two-stage (Section 2.3), variant 1 unrolled + barrier-free tree
+// (Section 3).  partial holds cap elements.
+hipError_t paper_design_reduce(const void* x, int64_t n, rd_dtype dt, int variant, int unroll, void* out,
+                               void* partial, int cap, int cus, hipStream_t s);
 
 }  // namespace rd

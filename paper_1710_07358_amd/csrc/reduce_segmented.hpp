@@ -236,30 +236,47 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
   const int64_t v0 = min(w * P.per, P.nvec), v1 = min((w + 1) * P.per, P.nvec);
   const u32x4* xv = (const u32x4*)(x + P.A);
   auto rel_vec = [&](int k) { return (int32_t)(((k / V) * 64 + lane) * V + (k % V)); };
+  // Windows of 64 x U vectors, software-pipelined: the next window's loads
+  // are issued before the current one is folded, so segment bookkeeping at
+  // boundaries overlaps memory latency.  Vectors at or past v1 are not read.
+  auto load_window = [&](int64_t vb, u32x4 (&raw)[U]) {
+    const int64_t nv = min((int64_t)(64 * U), v1 - vb);
+    if (nv == 64 * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        raw[u] = u32x4{0u, 0u, 0u, 0u};
+        if (u * 64 + lane < nv) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
+      }
+    }
+  };
+  u32x4 cur[U], nxt[U];
+  if (v0 < v1) load_window(v0, cur);
   for (int64_t vb = v0; vb < v1; vb += 64 * U) {
+    const int64_t vn = vb + 64 * U;
+    if (vn < v1) load_window(vn, nxt);
     const int64_t nv = min((int64_t)(64 * U), v1 - vb);
     const int64_t P0 = P.A + vb * V;
     A vals[K];
-    if (nv == 64 * U) {  // full window: unguarded loads
-      u32x4 raw[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
+    if (nv == 64 * U) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < V; ++e) vals[u * V + e] = R::convert(lane_elem<T>(raw[u], e));
-    } else {  // last window of the piece: only vectors below v1
+        for (int e = 0; e < V; ++e) vals[u * V + e] = R::convert(lane_elem<T>(cur[u], e));
+    } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = (u * 64 + lane) < nv;
-        u32x4 raw = u32x4{0u, 0u, 0u, 0u};
-        if (ok) raw = load16<NT>(xv + vb + u * 64 + lane);
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          vals[u * V + e] = ok ? R::convert(lane_elem<T>(raw, e)) : R::identity();
+          vals[u * V + e] = ok ? R::convert(lane_elem<T>(cur[u], e)) : R::identity();
       }
     }
     consume(vals, rel_vec, P0, P0 + nv * V);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }
 
   if (w == P.wt) {

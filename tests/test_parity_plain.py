@@ -204,3 +204,22 @@ def test_float_prod_powers_of_two_exact(dtype):
         expect = 2.0 ** int(e.sum())
         assert oracle.reduce(x, "prod", dtype) == expect
         assert value_of(out) == expect, (dtype, n)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+def test_paper_design_baselines(dtype):
+    # the paper's own designs (two-stage; unrolled with the barrier-free tree)
+    for n in (0, 1, 63, 1025, 5_533_214):
+        x_np = W.plain(n, dtype, "sum", config=0, salt=n)
+        x = to_gpu(x_np, dtype)
+        if dtype == "int32":
+            ref = oracle.reduce(x_np, "sum", dtype)
+        else:
+            ref, abs_sum = oracle.exact_sum(x_np)
+        for variant, unrolls in ((0, [1]), (1, [1, 2, 3, 4, 5, 6, 7, 8, 16])):
+            for f in unrolls:
+                out = rd.reduce_paper_design(x, variant, f)
+                if dtype == "int32":
+                    assert bits_of(out) == ref, (n, variant, f)
+                else:
+                    assert abs(value_of(out) - ref) <= 2.0 ** -20 * abs_sum, (n, variant, f)
