@@ -31,11 +31,14 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 OPS = {"sum": 0, "prod": 1, "min": 2, "max": 3, "and": 4, "or": 5, "xor": 6}
-DTYPES = {"int32": 0, "uint32": 1, "float32": 2, "float64": 3, "float16": 4, "bfloat16": 5}
+DTYPES = {"int32": 0, "uint32": 1, "float32": 2, "float64": 3, "float16": 4, "bfloat16": 5,
+          "int64": 6, "uint64": 7}
+INT_DTYPES = ("int32", "uint32", "int64", "uint64")
 FLOAT_DTYPES = ("float32", "float64", "float16", "bfloat16")
 BITWISE = ("and", "or", "xor")
 _STORAGE = {"int32": np.int32, "uint32": np.uint32, "float32": np.float32,
-            "float64": np.float64, "float16": np.uint16, "bfloat16": np.uint16}
+            "float64": np.float64, "float16": np.uint16, "bfloat16": np.uint16,
+            "int64": np.int64, "uint64": np.uint64}
 
 _lib = None
 
@@ -60,7 +63,9 @@ def _load():
         i64, vp, ci = ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
         dp = ctypes.POINTER(ctypes.c_double)
         lib.orc_fold_u32.argtypes = [vp, i64, ci, ci, ctypes.POINTER(ctypes.c_uint32)]
-        lib.orc_fold_u64.argtypes = [vp, i64, ci, ctypes.POINTER(ctypes.c_uint64)]
+        lib.orc_fold_u64.argtypes = [vp, i64, ci, ci, ctypes.POINTER(ctypes.c_uint64)]
+        lib.orc_argext_int.argtypes = [vp, i64, ci, ci, ci, ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_int64)]
         lib.orc_fold_u16.argtypes = [vp, i64, ci, ctypes.POINTER(ctypes.c_uint16)]
         lib.orc_load_float.argtypes = [vp, i64, ci]
         lib.orc_load_float.restype = ctypes.c_double
@@ -70,7 +75,7 @@ def _load():
         lib.orc_segmented.argtypes = [vp, vp, i64, ci, ci, vp]
         lib.orc_row_forward.argtypes = [vp, i64, i64, ci, vp, vp, vp]
         lib.orc_row_grad.argtypes = [vp, i64, i64, ci, vp, vp]
-        for f in (lib.orc_fold_u32, lib.orc_fold_u64, lib.orc_fold_u16, lib.orc_exact_sum,
+        for f in (lib.orc_fold_u32, lib.orc_fold_u64, lib.orc_fold_u16, lib.orc_argext_int, lib.orc_exact_sum,
                   lib.orc_prod, lib.orc_minmax, lib.orc_segmented, lib.orc_row_forward,
                   lib.orc_row_grad):
             f.restype = ctypes.c_int
@@ -117,11 +122,11 @@ def reduce(x: np.ndarray, op: str, dtype: str | None = None):
         out = ctypes.c_uint32()
         _check(lib.orc_fold_u32(_ptr(x), n, OPS[op], int(dtype == "int32"), ctypes.byref(out)), op)
         return out.value
+    if dtype in ("int64", "uint64") or (dtype == "float64" and op in BITWISE):
+        out64 = ctypes.c_uint64()
+        _check(lib.orc_fold_u64(_ptr(x), n, OPS[op], int(dtype == "int64"), ctypes.byref(out64)), op)
+        return out64.value
     if op in BITWISE:
-        if dtype == "float64":
-            out64 = ctypes.c_uint64()
-            _check(lib.orc_fold_u64(_ptr(x), n, OPS[op], ctypes.byref(out64)), op)
-            return out64.value
         out16 = ctypes.c_uint16()
         _check(lib.orc_fold_u16(_ptr(x), n, OPS[op], ctypes.byref(out16)), op)
         return out16.value
@@ -146,10 +151,18 @@ def exact_sum(x: np.ndarray, dtype: str | None = None) -> tuple[float, float]:
     return s.value, a.value
 
 
-def argextreme(x: np.ndarray, op: str, dtype: str | None = None) -> tuple[float, int]:
-    """(min or max value, lowest index attaining it; -1 when empty)."""
+def argextreme(x: np.ndarray, op: str, dtype: str | None = None) -> tuple:
+    """(min or max value, lowest index attaining it; -1 when empty).
+
+    Integer dtypes report the value as its unsigned bit pattern."""
     dtype = dtype or str(x.dtype)
     x = _storage(np.ravel(x), dtype)
+    if dtype in INT_DTYPES:
+        v, at = ctypes.c_uint64(), ctypes.c_int64()
+        width = 32 if dtype in ("int32", "uint32") else 64
+        _check(_load().orc_argext_int(_ptr(x), x.size, width, int(dtype.startswith("int")), int(op == "max"),
+                                      ctypes.byref(v), ctypes.byref(at)), op)
+        return v.value, at.value
     d, at = ctypes.c_double(), ctypes.c_int64()
     _check(_load().orc_minmax(_ptr(x), x.size, DTYPES[dtype], int(op == "max"),
                               ctypes.byref(d), ctypes.byref(at)), op)
@@ -171,7 +184,7 @@ def segmented(x: np.ndarray, offsets: np.ndarray, op: str, dtype: str | None = N
     x = _storage(np.ravel(x), dtype)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     nseg = offsets.size - 1
-    as_bits = dtype in ("int32", "uint32") or op in BITWISE
+    as_bits = dtype in INT_DTYPES or op in BITWISE
     out = np.empty(max(nseg, 0), dtype=np.uint64 if as_bits else np.float64)
     _check(_load().orc_segmented(_ptr(x), _ptr(offsets), nseg, DTYPES[dtype], OPS[op], _ptr(out)),
            "segmented")

@@ -30,7 +30,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { DT_I32 = 0, DT_U32 = 1, DT_F32 = 2, DT_F64 = 3, DT_F16 = 4, DT_BF16 = 5 };
+enum { DT_I32 = 0, DT_U32 = 1, DT_F32 = 2, DT_F64 = 3, DT_F16 = 4, DT_BF16 = 5, DT_I64 = 6, DT_U64 = 7 };
 enum { OP_SUM = 0, OP_PROD = 1, OP_MIN = 2, OP_MAX = 3, OP_AND = 4, OP_OR = 5, OP_XOR = 6 };
 
 /* ------------------------------------------------------------------ */
@@ -72,18 +72,65 @@ int orc_fold_u32(const uint32_t* x, int64_t n, int op, int is_signed, uint32_t* 
     return 0;
 }
 
-int orc_fold_u64(const uint64_t* x, int64_t n, int op, uint64_t* out) {
+int orc_fold_u64(const uint64_t* x, int64_t n, int op, int is_signed, uint64_t* out) {
     uint64_t acc;
-    if (op == OP_AND) acc = UINT64_MAX;
-    else if (op == OP_OR || op == OP_XOR) acc = 0u;
-    else return -1;
+    switch (op) { /* neutral elements */
+    case OP_SUM: acc = 0u; break;
+    case OP_PROD: acc = 1u; break;
+    case OP_MIN: acc = is_signed ? (uint64_t)INT64_MAX : UINT64_MAX; break;
+    case OP_MAX: acc = is_signed ? (uint64_t)INT64_MIN : 0u; break;
+    case OP_AND: acc = UINT64_MAX; break;
+    case OP_OR: acc = 0u; break;
+    case OP_XOR: acc = 0u; break;
+    default: return -1;
+    }
     if (n < 0) return -2;
     for (int64_t i = 0; i < n; ++i) {
-        if (op == OP_AND) acc &= x[i];
-        else if (op == OP_OR) acc |= x[i];
-        else acc ^= x[i];
+        uint64_t v = x[i];
+        switch (op) {
+        case OP_SUM: acc = acc + v; break; /* wraps mod 2^64 */
+        case OP_PROD: acc = acc * v; break;
+        case OP_MIN:
+            if (is_signed) acc = ((int64_t)v < (int64_t)acc) ? v : acc;
+            else acc = (v < acc) ? v : acc;
+            break;
+        case OP_MAX:
+            if (is_signed) acc = ((int64_t)v > (int64_t)acc) ? v : acc;
+            else acc = (v > acc) ? v : acc;
+            break;
+        case OP_AND: acc &= v; break;
+        case OP_OR: acc |= v; break;
+        case OP_XOR: acc ^= v; break;
+        }
     }
     *out = acc;
+    return 0;
+}
+
+/* Lowest index attaining the integer min (is_max = 0) or max of x, read as
+ * width-bit (32 or 64) signed or unsigned integers; -1 when n = 0. */
+int orc_argext_int(const void* x, int64_t n, int width, int is_signed, int is_max, uint64_t* value,
+                   int64_t* first) {
+    if (n < 0 || (width != 32 && width != 64)) return -2;
+    int64_t at = -1;
+    uint64_t best = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t v = width == 32 ? ((const uint32_t*)x)[i] : ((const uint64_t*)x)[i];
+        int better;
+        if (at < 0) better = 1;
+        else if (is_signed && width == 32)
+            better = is_max ? ((int32_t)v > (int32_t)best) : ((int32_t)v < (int32_t)best);
+        else if (is_signed)
+            better = is_max ? ((int64_t)v > (int64_t)best) : ((int64_t)v < (int64_t)best);
+        else
+            better = is_max ? (v > best) : (v < best);
+        if (better) {
+            best = v;
+            at = i;
+        }
+    }
+    *value = best;
+    *first = at;
     return 0;
 }
 
@@ -349,7 +396,8 @@ int orc_minmax(const void* x, int64_t n, int dtype, int is_max, double* out, int
 int orc_segmented(const void* x, const int64_t* offsets, int64_t nseg, int dtype, int op,
                   void* out) {
     if (nseg < 0) return -2;
-    size_t esz = (dtype == DT_F64) ? 8 : (dtype == DT_F16 || dtype == DT_BF16) ? 2 : 4;
+    size_t esz = (dtype == DT_F64 || dtype == DT_I64 || dtype == DT_U64) ? 8
+               : (dtype == DT_F16 || dtype == DT_BF16) ? 2 : 4;
     int bitwise = (op == OP_AND || op == OP_OR || op == OP_XOR);
     for (int64_t s = 0; s < nseg; ++s) {
         int64_t b = offsets[s], e = offsets[s + 1];
@@ -361,9 +409,9 @@ int orc_segmented(const void* x, const int64_t* offsets, int64_t nseg, int dtype
             uint32_t r;
             rc = orc_fold_u32((const uint32_t*)p, len, op, dtype == DT_I32, &r);
             ((uint64_t*)out)[s] = r;
-        } else if (bitwise && dtype == DT_F64) {
+        } else if (dtype == DT_I64 || dtype == DT_U64 || (bitwise && dtype == DT_F64)) {
             uint64_t r;
-            rc = orc_fold_u64((const uint64_t*)p, len, op, &r);
+            rc = orc_fold_u64((const uint64_t*)p, len, op, dtype == DT_I64, &r);
             ((uint64_t*)out)[s] = r;
         } else if (bitwise) {
             uint16_t r;

@@ -9,7 +9,8 @@
  * helper with the GPU path: type and operator codes below are this file's own.
  *
  * Conventions
- *   dtype codes : 0 int32, 1 uint32, 2 float32, 3 float64, 4 float16, 5 bfloat16
+ *   dtype codes : 0 int32, 1 uint32, 2 float32, 3 float64, 4 float16, 5 bfloat16,
+ *                 6 int64, 7 uint64
  *   op codes    : 0 sum, 1 product, 2 min, 3 max, 4 and, 5 or, 6 xor
  *   Every function takes host pointers, never allocates memory the caller must
  *   free, and returns 0 on success or a negative value for an unsupported
@@ -30,10 +31,17 @@ extern "C" {
  * when is_signed != 0, unsigned otherwise; and/or/xor act on the bits. */
 int orc_fold_u32(const uint32_t* x, int64_t n, int op, int is_signed, uint32_t* out);
 
-/* Bitwise and/or/xor left fold on 64-bit and 16-bit patterns (raw bits of
- * float64 and float16/bfloat16 data). */
-int orc_fold_u64(const uint64_t* x, int64_t n, int op, uint64_t* out);
+/* The same fold on 64-bit integers (+ and x wrap modulo 2^64; min/max signed
+ * when is_signed != 0); and/or/xor also serve the bits of float64 data. */
+int orc_fold_u64(const uint64_t* x, int64_t n, int op, int is_signed, uint64_t* out);
+
+/* Bitwise and/or/xor left fold on 16-bit patterns (float16/bfloat16 bits). */
 int orc_fold_u16(const uint16_t* x, int64_t n, int op, uint16_t* out);
+
+/* Integer min (is_max = 0) or max of width-bit (32 or 64) values, signed or
+ * unsigned, and the lowest index attaining it (-1 when n = 0). */
+int orc_argext_int(const void* x, int64_t n, int width, int is_signed, int is_max, uint64_t* value,
+                   int64_t* first);
 
 /* Value of element i of a float array of the given dtype, as a double
  * (exact for every supported float dtype). */

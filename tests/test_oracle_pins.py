@@ -406,3 +406,71 @@ def test_row_grad_prod_central_difference():
             dn[j] -= h
             fd = (np.prod(up) - np.prod(dn)) / (2 * h)
             assert abs(fd - grad[r, j]) <= 1e-9 * abs(grad[r, j])
+
+
+# ---------------------------------------------------------------- 64-bit integers
+
+M64 = 2 ** 64
+
+
+@pytest.mark.parametrize("n", [0, 1, 5, 1023, 100_003])
+def test_int64_sum_and_xor_closed_forms(n):
+    base = 2 ** 40  # values beyond 32 bits
+    x = (np.arange(1, n + 1, dtype=np.uint64) + np.uint64(base))
+    assert oracle.reduce(x, "sum", "uint64") == (n * (n + 1) // 2 + n * base) % M64
+    assert oracle.reduce(x.view(np.int64), "sum", "int64") == (n * (n + 1) // 2 + n * base) % M64
+    y = np.arange(n, dtype=np.uint64)
+    assert oracle.reduce(y, "xor", "uint64") == _xor_prefix(n - 1)
+
+
+def test_int64_min_max_signed_vs_unsigned():
+    rng = np.random.default_rng(64)
+    x = rng.integers(-2 ** 62, 2 ** 62, size=20_000, dtype=np.int64)
+    x[123] = -2 ** 63
+    x[777] = 2 ** 63 - 1
+    assert oracle.reduce(x, "min", "int64") == (-2 ** 63) % M64
+    assert oracle.reduce(x, "max", "int64") == 2 ** 63 - 1
+    u = x.view(np.uint64)
+    assert oracle.reduce(u, "min", "uint64") == min(int(v) for v in u)
+    assert oracle.reduce(u, "max", "uint64") == max(int(v) for v in u)
+
+
+def test_int64_prod_and_bitwise_vs_python():
+    rng = np.random.default_rng(65)
+    odd = rng.integers(0, 2 ** 62, size=5000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    expect = 1
+    for v in odd:
+        expect = (expect * int(v)) % M64
+    assert oracle.reduce(odd, "prod", "uint64") == expect
+    a = 0xFFFFFFFFFFFFFFFF
+    o = 0
+    for v in odd[:300]:
+        a &= int(v)
+        o |= int(v)
+    assert oracle.reduce(odd[:300], "and", "uint64") == a
+    assert oracle.reduce(odd[:300], "or", "uint64") == o
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "int64", "uint64"])
+def test_int_argextreme_lowest_index(dtype):
+    rng = np.random.default_rng(66)
+    x = rng.integers(0, 1000, size=10_000).astype(dtype)
+    x[[70, 9000, 4000]] = 5000   # ties for max: lowest index 70
+    x[[6000, 30]] = np.array(0, dtype=dtype) if dtype.startswith("u") else -7  # min ties
+    vals = [int(v) for v in x]
+    for op, f in (("max", max), ("min", min)):
+        v, at = oracle.argextreme(x, op, dtype)
+        width = 32 if dtype.endswith("32") else 64
+        assert v == f(vals) % (2 ** width)
+        assert at == vals.index(f(vals))
+    assert oracle.argextreme(np.zeros(0, dtype=dtype), "max", dtype)[1] == -1
+
+
+def test_segmented_int64_vs_python():
+    rng = np.random.default_rng(67)
+    lens = rng.integers(0, 200, size=100)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    x = rng.integers(-2 ** 62, 2 ** 62, size=int(off[-1]), dtype=np.int64)
+    out = oracle.segmented(x, off, "sum", "int64")
+    for s in range(100):
+        assert int(out[s]) == sum(int(v) for v in x[off[s]:off[s + 1]]) % M64
