@@ -24,7 +24,7 @@
  * - n = 0 (or an empty segment) yields the neutral element of the op:
  *   + -> 0, x -> 1, min -> +inf / INT32_MAX / UINT32_MAX,
  *   max -> -inf / INT32_MIN / 0, and -> all ones, or/xor -> 0.
- * - Integer + and x wrap modulo 2^32.  min/max on floats follow IEEE 754-2019
+ * - Integer + and x wrap modulo 2^32 (2^64 for the 64-bit dtypes).  min/max on floats follow IEEE 754-2019
  *   minimum/maximum: a NaN anywhere gives NaN, and -0 < +0.  and/or/xor on a
  *   float dtype act on the stored bit patterns.
  * - Float results are deterministic: the same input, size and configuration
@@ -46,7 +46,9 @@ typedef enum rd_dtype {
     RD_F32 = 2,  /* IEEE binary32 */
     RD_F64 = 3,  /* IEEE binary64 */
     RD_F16 = 4,  /* IEEE binary16 */
-    RD_BF16 = 5  /* bfloat16 (upper half of a binary32) */
+    RD_BF16 = 5, /* bfloat16 (upper half of a binary32) */
+    RD_I64 = 6,  /* int64 */
+    RD_U64 = 7   /* uint64 */
 } rd_dtype;
 
 typedef enum rd_op {

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librd.so")
 TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.txt")
 
 # enums of include/rd.h
-RD_I32, RD_U32, RD_F32, RD_F64, RD_F16, RD_BF16 = range(6)
+RD_I32, RD_U32, RD_F32, RD_F64, RD_F16, RD_BF16, RD_I64, RD_U64 = range(8)
 RD_SUM, RD_PROD, RD_MIN, RD_MAX, RD_AND, RD_OR, RD_XOR = range(7)
 RD_OK, RD_ERR_INVALID_ARG, RD_ERR_UNSUPPORTED, RD_ERR_HIP, RD_ERR_NOMEM, RD_ERR_CAPTURE, RD_ERR_WORKSPACE = (
     0, -1, -2, -3, -4, -5, -6)

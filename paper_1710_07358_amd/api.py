@@ -14,7 +14,8 @@ import torch
 from . import _native as N
 
 DTYPES = {torch.int32: N.RD_I32, torch.uint32: N.RD_U32, torch.float32: N.RD_F32,
-          torch.float64: N.RD_F64, torch.float16: N.RD_F16, torch.bfloat16: N.RD_BF16}
+          torch.float64: N.RD_F64, torch.float16: N.RD_F16, torch.bfloat16: N.RD_BF16,
+          torch.int64: N.RD_I64, torch.uint64: N.RD_U64}
 TORCH_DTYPE = {v: k for k, v in DTYPES.items()}
 OPS = {"sum": N.RD_SUM, "prod": N.RD_PROD, "min": N.RD_MIN, "max": N.RD_MAX,
        "and": N.RD_AND, "or": N.RD_OR, "xor": N.RD_XOR}

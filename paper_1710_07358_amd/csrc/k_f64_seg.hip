@@ -9,11 +9,8 @@ SegFn seg_f64(rd_op op, int u, bool nt) {
     case RD_PROD: return seg_pick<Red<Store::F64, Op::Prod>>(u, nt);
     case RD_MIN: return seg_pick<Red<Store::F64, Op::Min>>(u, nt);
     case RD_MAX: return seg_pick<Red<Store::F64, Op::Max>>(u, nt);
-    case RD_AND: return seg_pick<Red<Store::U64, Op::And>>(u, nt);
-    case RD_OR: return seg_pick<Red<Store::U64, Op::Or>>(u, nt);
-    case RD_XOR: return seg_pick<Red<Store::U64, Op::Xor>>(u, nt);
+    default: return seg_bits64(op, u, nt);
   }
-  return nullptr;
 }
 
 }  // namespace rd

@@ -229,7 +229,7 @@ rd::Launch row_launch(rd_kind kind, rd_op op, int64_t rows, int64_t cols) {
   return rd::Launch{256, c.blocks_per_cu, c.unroll > 8 ? 8 : c.unroll, c.nontemporal != 0, c.layout};
 }
 
-bool valid_dtype(rd_dtype dt) { return dt >= RD_I32 && dt <= RD_BF16; }
+bool valid_dtype(rd_dtype dt) { return dt >= RD_I32 && dt <= RD_U64; }
 bool valid_op(rd_op op) { return op >= RD_SUM && op <= RD_XOR; }
 
 rd_status check_ptr(const void* p, size_t align, const char* name) {
@@ -250,6 +250,8 @@ PlainFn plain_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
     case RD_F64: return plain_f64(op, unroll, nt);
     case RD_F16:
     case RD_BF16: return plain_half(dt, op, unroll, nt);
+    case RD_I64:
+    case RD_U64: return plain_int64(dt, op, unroll, nt);
   }
   return nullptr;
 }
@@ -271,6 +273,8 @@ SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
     case RD_F64: return seg_f64(op, unroll, nt);
     case RD_F16:
     case RD_BF16: return seg_half(dt, op, unroll, nt);
+    case RD_I64:
+    case RD_U64: return seg_int64(dt, op, unroll, nt);
   }
   return nullptr;
 }
@@ -288,7 +292,7 @@ rd_status rd_init(void) {
 size_t rd_dtype_size(rd_dtype dt) {
   switch (dt) {
     case RD_I32: case RD_U32: case RD_F32: return 4;
-    case RD_F64: return 8;
+    case RD_F64: case RD_I64: case RD_U64: return 8;
     case RD_F16: case RD_BF16: return 2;
   }
   return 0;

@@ -60,13 +60,33 @@ template <Op O> struct Combiner<O, int32_t> {  // signed min/max only
   }
 };
 
-template <Op O> struct Combiner<O, uint64_t> {  // bitwise ops on 64-bit patterns
-  static_assert(O == Op::And || O == Op::Or || O == Op::Xor, "64-bit integers serve and/or/xor");
-  static __device__ __forceinline__ uint64_t identity() { return O == Op::And ? ~0ull : 0ull; }
+// 64-bit unsigned: + and x wrap modulo 2^64; bitwise ops (also the bits of
+// float64 data); unsigned min/max.
+template <Op O> struct Combiner<O, uint64_t> {
+  static __device__ __forceinline__ uint64_t identity() {
+    if constexpr (O == Op::Sum || O == Op::Or || O == Op::Xor || O == Op::Max) return 0ull;
+    else if constexpr (O == Op::Prod) return 1ull;
+    else return ~0ull;  // And, Min
+  }
   static __device__ __forceinline__ uint64_t apply(uint64_t a, uint64_t b) {
-    if constexpr (O == Op::And) return a & b;
+    if constexpr (O == Op::Sum) return a + b;
+    else if constexpr (O == Op::Prod) return a * b;
+    else if constexpr (O == Op::Min) return a < b ? a : b;
+    else if constexpr (O == Op::Max) return a > b ? a : b;
+    else if constexpr (O == Op::And) return a & b;
     else if constexpr (O == Op::Or) return a | b;
     else return a ^ b;
+  }
+};
+
+template <Op O> struct Combiner<O, int64_t> {  // signed 64-bit min/max only
+  static_assert(O == Op::Min || O == Op::Max, "signed accumulators serve min/max");
+  static __device__ __forceinline__ int64_t identity() {
+    return O == Op::Min ? (int64_t)0x7FFFFFFFFFFFFFFFll : (int64_t)(-0x7FFFFFFFFFFFFFFFll - 1);
+  }
+  static __device__ __forceinline__ int64_t apply(int64_t a, int64_t b) {
+    if constexpr (O == Op::Min) return a < b ? a : b;
+    else return a > b ? a : b;
   }
 };
 
@@ -92,12 +112,13 @@ template <Op O> struct Combiner<O, double> : FloatCombiner<O, double> {};
 
 // Storage kinds: how a stored element becomes an accumulator value and how
 // the final accumulator becomes the output element.
-enum class Store { U32, I32, U64, F32, F64, F16, BF16, U16 };
+enum class Store { U32, I32, U64, I64, F32, F64, F16, BF16, U16 };
 
 template <Store S> struct Stored;
 template <> struct Stored<Store::U32> { using T = uint32_t; };
 template <> struct Stored<Store::I32> { using T = int32_t; };
 template <> struct Stored<Store::U64> { using T = uint64_t; };
+template <> struct Stored<Store::I64> { using T = int64_t; };
 template <> struct Stored<Store::F32> { using T = float; };
 template <> struct Stored<Store::F64> { using T = double; };
 template <> struct Stored<Store::F16> { using T = uint16_t; };

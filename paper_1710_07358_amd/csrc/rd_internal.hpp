@@ -57,7 +57,9 @@ SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nontemporal);
 PlainFn plain_int(rd_dtype dt, rd_op op, int unroll, bool nt);  // RD_I32 / RD_U32
 PlainFn plain_bits32(rd_op op, int unroll, bool nt);
 PlainFn plain_f32(rd_op op, int unroll, bool nt);
-PlainFn plain_f64(rd_op op, int unroll, bool nt);  // includes 64-bit bitwise
+PlainFn plain_f64(rd_op op, int unroll, bool nt);
+PlainFn plain_int64(rd_dtype dt, rd_op op, int unroll, bool nt);  // RD_I64 / RD_U64
+PlainFn plain_bits64(rd_op op, int unroll, bool nt);
 PlainFn plain_half(rd_dtype dt, rd_op op, int unroll, bool nt);  // RD_F16 / RD_BF16, 16-bit bitwise
 PlainFn comp_f32(int unroll, bool nt);
 PlainFn comp_half(rd_dtype dt, int unroll, bool nt);
@@ -65,6 +67,8 @@ SegFn seg_int(rd_dtype dt, rd_op op, int unroll, bool nt);
 SegFn seg_bits32(rd_op op, int unroll, bool nt);
 SegFn seg_f32(rd_op op, int unroll, bool nt);
 SegFn seg_f64(rd_op op, int unroll, bool nt);
+SegFn seg_int64(rd_dtype dt, rd_op op, int unroll, bool nt);
+SegFn seg_bits64(rd_op op, int unroll, bool nt);
 SegFn seg_half(rd_dtype dt, rd_op op, int unroll, bool nt);
 
 // Row-wise forward / backward (float32).  Launch: grid = work-groups per CU

@@ -27,12 +27,15 @@ import numpy as np
 
 BASE_SEED = 171007358
 OP_INDEX = {"sum": 0, "prod": 1, "min": 2, "max": 3, "and": 4, "or": 5, "xor": 6}
-DTYPE_INDEX = {"int32": 0, "uint32": 1, "float32": 2, "float64": 3, "float16": 4, "bfloat16": 5}
+DTYPE_INDEX = {"int32": 0, "uint32": 1, "float32": 2, "float64": 3, "float16": 4, "bfloat16": 5,
+               "int64": 6, "uint64": 7}
 BITWISE = ("and", "or", "xor")
 # numpy storage type of each dtype (bf16 and fp16 travel as uint16 bit patterns)
 STORAGE = {"int32": np.int32, "uint32": np.uint32, "float32": np.float32,
-           "float64": np.float64, "float16": np.uint16, "bfloat16": np.uint16}
-ELEM_BYTES = {"int32": 4, "uint32": 4, "float32": 4, "float64": 8, "float16": 2, "bfloat16": 2}
+           "float64": np.float64, "float16": np.uint16, "bfloat16": np.uint16,
+           "int64": np.int64, "uint64": np.uint64}
+ELEM_BYTES = {"int32": 4, "uint32": 4, "float32": 4, "float64": 8, "float16": 2, "bfloat16": 2,
+              "int64": 8, "uint64": 8}
 
 # log-normal sigma giving mean length 4 x median: 1024 * exp(s^2/2) = 4096
 SEGMENT_SIGMA = math.sqrt(2.0 * math.log(4.0))
@@ -91,6 +94,14 @@ def plain(n: int, dtype: str, op: str, config: int = 1, salt: int = 0) -> np.nda
         if op in BITWISE:
             return rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
         return rng.integers(0, 1000, size=n, endpoint=True, dtype=np.uint32)
+    if dtype == "int64":
+        if op in BITWISE:
+            return rng.integers(0, 2 ** 64 - 1, size=n, dtype=np.uint64, endpoint=True).view(np.int64)
+        return rng.integers(-1000, 1000, size=n, endpoint=True, dtype=np.int64)
+    if dtype == "uint64":
+        if op in BITWISE:
+            return rng.integers(0, 2 ** 64 - 1, size=n, dtype=np.uint64, endpoint=True)
+        return rng.integers(0, 1000, size=n, endpoint=True, dtype=np.uint64)
     if op in BITWISE:  # raw bit patterns of float data: use ordinary float draws
         lo, hi = -1.0, 1.0
     elif op == "prod":
@@ -105,6 +116,9 @@ def plain(n: int, dtype: str, op: str, config: int = 1, salt: int = 0) -> np.nda
 def odd_int_supplement(n: int, dtype: str, salt: int = 0) -> np.ndarray:
     """Odd 32-bit integers: units modulo 2^32, so an integer product stays nonzero."""
     rng = generator(1, "prod", dtype, salt + 7)
+    if dtype in ("int64", "uint64"):
+        v = rng.integers(0, 2 ** 63, size=n, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        return v.view(np.int64) if dtype == "int64" else v
     v = rng.integers(0, 2 ** 31, size=n, dtype=np.uint64) * 2 + 1
     return v.astype(np.uint32).view(np.int32 if dtype == "int32" else np.uint32)
 

@@ -13,7 +13,9 @@ torch = pytest.importorskip("torch")
 FLOAT = ("float32", "float64", "float16", "bfloat16")
 BITWISE = ("and", "or", "xor")
 TORCH = {"int32": torch.int32, "uint32": torch.uint32, "float32": torch.float32,
-         "float64": torch.float64, "float16": torch.float16, "bfloat16": torch.bfloat16}
+         "float64": torch.float64, "float16": torch.float16, "bfloat16": torch.bfloat16,
+         "int64": torch.int64, "uint64": torch.uint64}
+INTS = ("int32", "uint32", "int64", "uint64")
 
 
 def gpu_available() -> bool:
@@ -28,6 +30,8 @@ def to_gpu(a: np.ndarray, dtype: str, pad_front: int = 0) -> torch.Tensor:
         host = torch.from_numpy(a.view(np.int16).copy()).view(TORCH[dtype])
     elif dtype == "uint32":
         host = torch.from_numpy(a.view(np.int32).copy()).view(torch.uint32)
+    elif dtype == "uint64":
+        host = torch.from_numpy(a.view(np.int64).copy()).view(torch.uint64)
     else:
         host = torch.from_numpy(a.copy())
     if pad_front:
@@ -62,7 +66,7 @@ def check_against_oracle(gpu_out: torch.Tensor, ref, x: np.ndarray, op: str, dty
                          abs_sum: float | None = None, compensated: bool = False):
     """Assert the GPU result matches the oracle to the bar for (op, dtype)."""
     n = x.size
-    if dtype in ("int32", "uint32") or op in BITWISE:
+    if dtype in INTS or op in BITWISE:
         got = bits_of(gpu_out)
         assert got == ref, f"{op}/{dtype} n={n}: got {got:#x}, oracle {ref:#x}"
         return

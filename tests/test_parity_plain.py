@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import TORCH, check_against_oracle, gpu_available, same_float, to_gpu, value_of, bits_of
+from helpers import INTS, TORCH, check_against_oracle, gpu_available, same_float, to_gpu, value_of, bits_of
 from paper_1710_07358_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -26,7 +26,7 @@ def _run(x_np, op, dtype, pad=0, compensated=False):
     out = rd.reduce_compensated(x) if compensated else rd.reduce(x, op)
     torch.cuda.synchronize()
     abs_sum = None
-    if op == "sum" and dtype not in ("int32", "uint32"):
+    if op == "sum" and dtype not in INTS:
         ref, abs_sum = oracle.exact_sum(x_np, dtype)
     else:
         ref = oracle.reduce(x_np, op, dtype)
@@ -42,7 +42,7 @@ def test_plain_small_workload(op, dtype):
     _run(x, op, dtype)
 
 
-@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64"])
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "int64", "uint64"])
 @pytest.mark.parametrize("op", OPS)
 def test_plain_sweep(op, dtype):
     for n in SWEEP_N:
@@ -58,7 +58,7 @@ def test_plain_half_dtypes(op, dtype):
         _run(x, op, dtype)
 
 
-@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16"])
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16", "int64"])
 @pytest.mark.parametrize("op", ["sum", "max", "xor"])
 def test_plain_misaligned_base(op, dtype):
     for pad in (1, 2, 3):
@@ -67,7 +67,7 @@ def test_plain_misaligned_base(op, dtype):
             _run(x, op, dtype, pad=pad)
 
 
-@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16"])
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16", "int64", "uint64"])
 @pytest.mark.parametrize("op", OPS)
 def test_plain_empty_is_identity(op, dtype):
     x = np.zeros(0, dtype=W.STORAGE[dtype])
@@ -75,7 +75,7 @@ def test_plain_empty_is_identity(op, dtype):
 
 
 def test_int_prod_odd_supplement():
-    for dtype in ("int32", "uint32"):
+    for dtype in INTS:
         x = W.odd_int_supplement(2 ** 20 + 7, dtype)
         _run(x, "prod", dtype)
 

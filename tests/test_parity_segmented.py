@@ -20,13 +20,14 @@ import paper_1710_07358_amd as rd  # noqa: E402
 def _gpu_out_as_oracle(out: torch.Tensor, dtype: str, op: str) -> np.ndarray:
     """GPU segment results in the oracle's representation (uint64 bits or float64)."""
     o = out.cpu()
-    if dtype in ("int32", "uint32") or op in ("and", "or", "xor"):
+    if dtype in ("int32", "uint32", "int64", "uint64") or op in ("and", "or", "xor"):
         size = o.element_size()
         view = {2: torch.int16, 4: torch.int32, 8: torch.int64}[size]
         v = o.view(view).numpy().astype(np.int64)
         if size < 8:
             v = v % (1 << (8 * size))
-        return v.astype(np.uint64)
+            return v.astype(np.uint64)
+        return o.view(torch.int64).numpy().view(np.uint64)
     return o.to(torch.float64).numpy()
 
 
@@ -34,7 +35,7 @@ def check_segments(x_np, off, op, dtype, out):
     got = _gpu_out_as_oracle(out, dtype, op)
     ref = oracle.segmented(x_np, off, op, dtype)
     nseg = len(off) - 1
-    if dtype in ("int32", "uint32") or op in ("and", "or", "xor"):
+    if dtype in ("int32", "uint32", "int64", "uint64") or op in ("and", "or", "xor"):
         bad = np.nonzero(got != ref)[0]
         assert bad.size == 0, f"{op}/{dtype}: {bad.size} segments differ, first {bad[:5]}"
         return
@@ -76,7 +77,7 @@ def mixed_lengths(rng, nseg, big=40_000):
     return lens.astype(np.int64)
 
 
-@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16"])
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "float32", "float64", "float16", "bfloat16", "int64", "uint64"])
 @pytest.mark.parametrize("op", ["sum", "prod", "min", "max", "and", "or", "xor"])
 def test_segmented_mixed_lengths(op, dtype):
     rng = np.random.default_rng(hash((op, dtype)) % 2 ** 32)
