@@ -141,6 +141,17 @@ rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
 rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out,
                                 rd_workspace* ws, void* stream);
 
+/* Minimum or maximum together with the LOWEST index attaining it, one launch.
+ *   dt        : any dtype;  op : RD_MIN or RD_MAX (else RD_ERR_UNSUPPORTED)
+ *   value_out : device pointer to one element of dtype dt -- exactly the
+ *               stored element at *index_out
+ *   index_out : device pointer to one int64
+ * Integers compare signed or unsigned by dtype; floats follow IEEE 754-2019
+ * (a NaN wins and its first index is returned; -0 < +0).  n = 0 gives the
+ * neutral element and index -1. */
+rd_status rd_argreduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* value_out,
+                       int64_t* index_out, rd_workspace* ws, void* stream);
+
 /* The two designs the paper describes, kept as measured baselines (sum of
  * int32, wrapping, or float32; out: device pointer to one element):
  *   variant 0: the two-stage reduction of Section 2.3 -- as many work-items as

@@ -45,6 +45,7 @@ SIGNATURES = {
     "rd_reduce_compensated": (_ci, [_vp, _i64, _ci, _vp, _vp, _vp]),
     "rd_segmented_reduce": (_ci, [_vp, _vp, _i64, _ci, _ci, _vp, _vp, _vp]),
     "rd_reduce_paper_design": (_ci, [_vp, _i64, _ci, _ci, _ci, _vp, _vp, _vp]),
+    "rd_argreduce": (_ci, [_vp, _i64, _ci, _ci, _vp, _vp, _vp, _vp]),
     "rd_saved_bytes": (_sz, [_ci, _i64, _i64]),
     "rd_rowreduce_fwd": (_ci, [_vp, _i64, _i64, _ci, _ci, _vp, _vp, _vp]),
     "rd_rowreduce_bwd": (_ci, [_vp, _vp, _vp, _i64, _i64, _ci, _ci, _vp, _vp]),

@@ -121,6 +121,19 @@ def reduce_compensated(x: torch.Tensor, out: torch.Tensor | None = None,
     return out
 
 
+def argreduce(x: torch.Tensor, op: str, workspace: Workspace | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """(min or max value, lowest index attaining it) of a contiguous device tensor."""
+    x = _dev_tensor(x, "x")
+    if op not in ("min", "max"):
+        raise ValueError("argreduce: op must be 'min' or 'max'")
+    value = torch.empty((), dtype=x.dtype, device=x.device)
+    index = torch.empty((), dtype=torch.int64, device=x.device)
+    with torch.cuda.device(x.device):
+        N.check(N.lib().rd_argreduce(x.data_ptr() if x.numel() else None, x.numel(), _dt(x), _op(op),
+                                     value.data_ptr(), index.data_ptr(), _ws(workspace), _stream(x.device)))
+    return value, index
+
+
 def reduce_paper_design(x: torch.Tensor, variant: int, unroll: int = 1, out: torch.Tensor | None = None,
                         workspace: Workspace | None = None) -> torch.Tensor:
     """Sum by one of the paper's own designs (variant 0: two-stage; 1: unrolled

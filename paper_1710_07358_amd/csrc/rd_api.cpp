@@ -405,6 +405,30 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_segmented_reduce launch");
 }
 
+rd_status rd_argreduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* value_out, int64_t* index_out,
+                       rd_workspace* ws, void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "rd_argreduce: invalid dtype %d", (int)dt);
+  if (op != RD_MIN && op != RD_MAX) return fail(RD_ERR_UNSUPPORTED, "rd_argreduce: op must be RD_MIN or RD_MAX");
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "rd_argreduce: n < 0");
+  const size_t es = rd_dtype_size(dt);
+  rd_status st;
+  if (n > 0 && (st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(value_out, es, "value_out")) != RD_OK) return st;
+  if ((st = check_ptr(index_out, 8, "index_out")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  rd_config cfg = choose_config(RD_KIND_PLAIN, dt, op, n);
+  cfg.unroll = cfg.unroll < 2 ? 2 : (cfg.unroll > 8 ? 8 : cfg.unroll);
+  rd::ArgFn fn = rd::arg_launcher(dt, op == RD_MAX, cfg.unroll, cfg.nontemporal != 0);
+  if (!fn) return fail(RD_ERR_UNSUPPORTED, "rd_argreduce: no kernel for dtype %d", (int)dt);
+  const rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, info.cus, (int)w->scratch.partial_cap);
+  hipError_t e = fn(n > 0 ? x : value_out, n, value_out, index_out, w->scratch, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_argreduce launch");
+}
+
 rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int variant, int unroll, void* out,
                                  rd_workspace* ws, void* stream) {
   if (dt != RD_F32 && dt != RD_I32)

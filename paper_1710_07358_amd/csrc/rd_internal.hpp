@@ -45,6 +45,11 @@ using PlainFn = hipError_t (*)(const void* x, int64_t n, void* out, const Scratc
                                const Launch& l, hipStream_t s);
 using SegFn = hipError_t (*)(const void* x, const int64_t* offsets, int64_t nseg, void* out,
                              const Scratch& ws, const Launch& l, hipStream_t s);
+using ArgFn = hipError_t (*)(const void* x, int64_t n, void* value_out, int64_t* index_out,
+                             const Scratch& ws, const Launch& l, hipStream_t s);
+
+// Arg-reduction (min/max with the lowest index); unroll 2, 4 or 8.
+ArgFn arg_launcher(rd_dtype dt, bool is_max, int unroll, bool nontemporal);
 
 // nullptr when (dt, op) is not offered or the unroll has no instantiation
 // (plain/compensated: 1, 2, 4, 8, 16; segmented: 2, 4, 8).
