@@ -136,7 +136,23 @@ __global__ __launch_bounds__(1024) void argreduce_kernel(const typename Stored<S
   const int64_t step = B * U;
   const int64_t nfull = nvec / step;
   const ChunkWalk walk = chunk_walk(layout, nfull);
-  for (int64_t c = walk.first; c < walk.end; c += walk.step) {
+  // The first chunk seeds every slot with a real element (even one equal to
+  // the neutral element, whose bits would not register as a change).
+  if (walk.first < walk.end) {
+    const int64_t c = walk.first;
+    const u32x4* p = xv + c * step + tid;
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load16<NT>(p + u * B);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        best[u][e] = arg_convert<S>(lane_elem<T>(v[u], e));
+        at[u][e] = (int32_t)c;
+      }
+  }
+  for (int64_t c = walk.first + walk.step; c < walk.end; c += walk.step) {
     const u32x4* p = xv + c * step + tid;
     u32x4 v[U];
 #pragma unroll
