@@ -12,7 +12,9 @@ It wraps ``oracle.c`` (plain C, built with gcc, no fast-math) through ctypes:
 * float products: a double-double left fold;
 * float min/max: IEEE 754-2019 minimum/maximum (NaN wins, -0 < +0), with the
   lowest attaining index;
-* segmented and row-wise forms, and row-wise gradients.
+* segmented and row-wise forms, and row-wise gradients;
+* scans (the prefix form of the reduction), plain or restarted at segment
+  heads.
 
 Arrays are numpy arrays on the host.  bfloat16 data travels as ``uint16``
 bit patterns with ``dtype="bfloat16"``; float16 may be ``np.float16`` or
@@ -73,10 +75,11 @@ def _load():
         lib.orc_prod.argtypes = [vp, i64, ci, dp]
         lib.orc_minmax.argtypes = [vp, i64, ci, ci, dp, ctypes.POINTER(ctypes.c_int64)]
         lib.orc_segmented.argtypes = [vp, vp, i64, ci, ci, vp]
+        lib.orc_scan.argtypes = [vp, i64, ci, ci, ci, vp, i64, vp]
         lib.orc_row_forward.argtypes = [vp, i64, i64, ci, vp, vp, vp]
         lib.orc_row_grad.argtypes = [vp, i64, i64, ci, vp, vp]
         for f in (lib.orc_fold_u32, lib.orc_fold_u64, lib.orc_fold_u16, lib.orc_argext_int, lib.orc_exact_sum,
-                  lib.orc_prod, lib.orc_minmax, lib.orc_segmented, lib.orc_row_forward,
+                  lib.orc_prod, lib.orc_minmax, lib.orc_segmented, lib.orc_scan, lib.orc_row_forward,
                   lib.orc_row_grad):
             f.restype = ctypes.c_int
         _lib = lib
@@ -188,6 +191,23 @@ def segmented(x: np.ndarray, offsets: np.ndarray, op: str, dtype: str | None = N
     out = np.empty(max(nseg, 0), dtype=np.uint64 if as_bits else np.float64)
     _check(_load().orc_segmented(_ptr(x), _ptr(offsets), nseg, DTYPES[dtype], OPS[op], _ptr(out)),
            "segmented")
+    return out
+
+
+def scan(x: np.ndarray, op: str, dtype: str | None = None, exclusive: bool = False,
+         heads: np.ndarray | None = None) -> np.ndarray:
+    """Inclusive (or exclusive) scan: out[i] = x[r] (op) ... (op) x[i] over i's run.
+
+    Runs start at position 0 and at every position in ``heads`` (nondecreasing;
+    CSR segment offsets give the per-segment scan).  float64 results for float
+    data with sum/prod/min/max, else uint64 bit patterns (zero-extended)."""
+    dtype = dtype or str(x.dtype)
+    x = _storage(np.ravel(x), dtype)
+    h = np.ascontiguousarray(np.zeros(0) if heads is None else heads, dtype=np.int64)
+    as_bits = dtype in INT_DTYPES or op in BITWISE
+    out = np.empty(x.size, dtype=np.uint64 if as_bits else np.float64)
+    _check(_load().orc_scan(_ptr(x), x.size, DTYPES[dtype], OPS[op], int(bool(exclusive)),
+                            _ptr(h), h.size, _ptr(out)), "scan")
     return out
 
 

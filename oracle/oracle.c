@@ -254,9 +254,8 @@ static void la_add_double(longacc* a, double v, int force_positive) {
     la_add(a, mant, exp2 + 1074, negate);
 }
 
-static int la_bit(const uint32_t* mag, int k) { return (int)((mag[k >> 5] >> (k & 31)) & 1u); }
-
-/* Round the accumulated integer times 2^-1074 to the nearest double, ties to even. */
+/* Round the accumulated integer times 2^-1074 to the nearest double, ties to
+ * even.  Works digit by digit (base 2^32) so that rounding costs O(digits). */
 static double la_round(longacc* a) {
     la_normalize(a);
     uint32_t mag[LA_DIGITS];
@@ -273,21 +272,30 @@ static double la_round(longacc* a) {
     } else {
         for (int i = 0; i < LA_DIGITS; ++i) mag[i] = (uint32_t)a->d[i];
     }
-    int top = -1;
-    for (int k = LA_DIGITS * 32 - 1; k >= 0; --k)
-        if (la_bit(mag, k)) { top = k; break; }
-    if (top < 0) return 0.0;
+    int td = LA_DIGITS - 1;
+    while (td >= 0 && mag[td] == 0) --td;
+    if (td < 0) return 0.0;
+    int tb = 31;
+    while (!((mag[td] >> tb) & 1u)) --tb;
+    const int top = td * 32 + tb; /* index of the leading one bit */
+    /* the 96 bits below and including the leading digit, left-aligned */
+    uint64_t hi = ((uint64_t)mag[td] << 32) | (td >= 1 ? mag[td - 1] : 0u);
+    uint64_t lo3 = td >= 2 ? mag[td - 2] : 0u;
+    int sticky_digits = 0;
+    for (int i = td - 3; i >= 0 && !sticky_digits; --i) sticky_digits = mag[i] != 0;
+    /* shift so the leading one sits at bit 63 of w (w holds 64 bits; rest -> below) */
+    const int lead = 63 - (32 + tb);   /* bits to shift hi left */
+    uint64_t w = lead ? (hi << lead) | (lo3 >> (32 - lead)) : hi;
+    const uint64_t below = lead ? (lo3 << (32 + lead)) & 0xFFFFFFFFFFFFFFFFull : (lo3 << 32);
     double r;
     if (top < 53) {
-        uint64_t m = 0;
-        for (int k = top; k >= 0; --k) m = (m << 1) | (uint64_t)la_bit(mag, k);
-        r = ldexp((double)m, -1074); /* exact */
+        /* the whole value fits in 53 bits: exact */
+        uint64_t m = w >> (63 - top);
+        r = ldexp((double)m, -1074);
     } else {
-        uint64_t t = 0;
-        for (int k = top; k >= top - 52; --k) t = (t << 1) | (uint64_t)la_bit(mag, k);
-        int round_bit = la_bit(mag, top - 53);
-        int sticky = 0;
-        for (int k = top - 54; k >= 0 && !sticky; --k) sticky = la_bit(mag, k);
+        uint64_t t = w >> 11;                 /* 53 leading bits */
+        int round_bit = (int)((w >> 10) & 1u);
+        int sticky = ((w & 0x3FFu) != 0) || below != 0 || sticky_digits;
         if (round_bit && (sticky || (t & 1u))) ++t;
         int e = top - 52 - 1074;
         if (t == ((uint64_t)1 << 53)) { t >>= 1; ++e; }
@@ -425,6 +433,129 @@ int orc_segmented(const void* x, const int64_t* offsets, int64_t nseg, int dtype
             rc = orc_minmax(p, len, dtype, op == OP_MAX, &((double*)out)[s], 0);
         }
         if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Scan (the prefix form of the reduction).                             */
+/*                                                                      */
+/* out[i] combines the elements of i's run up to and including i        */
+/* (inclusive) or strictly before i (exclusive; the neutral element at  */
+/* the first position of a run).  Position 0 and every position listed  */
+/* in heads (nondecreasing; values outside [0, n) are ignored) start a  */
+/* run, so a plain scan has no heads and a segmented scan over CSR      */
+/* offsets passes the offsets.                                          */
+/* ------------------------------------------------------------------ */
+
+/* a (op) b on width-bit integers (signed comparison for min/max when is_signed). */
+static uint64_t int_combine(uint64_t a, uint64_t b, int op, int width, int is_signed) {
+    const uint64_t mask = width == 64 ? ~(uint64_t)0 : (((uint64_t)1 << width) - 1);
+    uint64_t r;
+    switch (op) {
+    case OP_SUM: r = a + b; break;
+    case OP_PROD: r = a * b; break;
+    case OP_AND: r = a & b; break;
+    case OP_OR: r = a | b; break;
+    case OP_XOR: r = a ^ b; break;
+    default: {
+        int less;
+        if (is_signed && width == 32) less = (int32_t)(uint32_t)a < (int32_t)(uint32_t)b;
+        else if (is_signed && width == 64) less = (int64_t)a < (int64_t)b;
+        else less = a < b;
+        r = (op == OP_MIN) ? (less ? a : b) : (less ? b : a);
+    }
+    }
+    return r & mask;
+}
+
+static uint64_t int_identity(int op, int width, int is_signed) {
+    const uint64_t mask = width == 64 ? ~(uint64_t)0 : (((uint64_t)1 << width) - 1);
+    const uint64_t sign = (uint64_t)1 << (width - 1);
+    switch (op) {
+    case OP_PROD: return 1u;
+    case OP_AND: return mask;
+    case OP_MIN: return is_signed ? sign - 1 : mask;
+    case OP_MAX: return is_signed ? sign : 0u;
+    default: return 0u; /* sum, or, xor */
+    }
+}
+
+/* Running state of one run of a scan. */
+typedef struct {
+    int as_int, op, dtype, width, is_signed;
+    uint64_t iacc;                    /* integer and bitwise ops */
+    longacc* sum;                     /* float sum: exact */
+    int sum_nan, sum_pinf, sum_ninf;
+    dd prod;                          /* float product */
+    double ext;                       /* float min/max */
+} scan_state;
+
+static void scan_restart(scan_state* st) {
+    if (st->as_int) st->iacc = int_identity(st->op, st->width, st->is_signed);
+    else if (st->op == OP_SUM) {
+        la_init(st->sum);
+        st->sum_nan = st->sum_pinf = st->sum_ninf = 0;
+    } else if (st->op == OP_PROD) {
+        st->prod.hi = 1.0;
+        st->prod.lo = 0.0;
+    } else st->ext = (st->op == OP_MAX) ? -INFINITY : INFINITY;
+}
+
+static void scan_fold(scan_state* st, const void* x, int64_t i) {
+    if (st->as_int) {
+        uint64_t v = st->width == 64 ? ((const uint64_t*)x)[i]
+                   : st->width == 32 ? ((const uint32_t*)x)[i] : ((const uint16_t*)x)[i];
+        st->iacc = int_combine(st->iacc, v, st->op, st->width, st->is_signed);
+        return;
+    }
+    double v = orc_load_float(x, i, st->dtype);
+    if (st->op == OP_SUM) {
+        if (isnan(v)) st->sum_nan = 1;
+        else if (isinf(v)) { if (v > 0) st->sum_pinf = 1; else st->sum_ninf = 1; }
+        else la_add_double(st->sum, v, 0);
+    } else if (st->op == OP_PROD) {
+        st->prod = dd_mul_double(st->prod, v);
+    } else if (!isnan(st->ext) && (isnan(v) || strictly_better(v, st->ext, st->op == OP_MAX))) {
+        st->ext = v; /* a NaN, once in, stays */
+    }
+}
+
+static void scan_emit(scan_state* st, void* out, int64_t i) {
+    if (st->as_int) ((uint64_t*)out)[i] = st->iacc;
+    else if (st->op == OP_SUM) {
+        double r = la_round(st->sum);
+        if (st->sum_nan || (st->sum_pinf && st->sum_ninf)) r = NAN;
+        else if (st->sum_pinf) r = INFINITY;
+        else if (st->sum_ninf) r = -INFINITY;
+        ((double*)out)[i] = r;
+    } else if (st->op == OP_PROD) ((double*)out)[i] = st->prod.hi + st->prod.lo;
+    else ((double*)out)[i] = st->ext;
+}
+
+int orc_scan(const void* x, int64_t n, int dtype, int op, int exclusive, const int64_t* heads,
+             int64_t nheads, void* out) {
+    if (n < 0 || nheads < 0 || op < OP_SUM || op > OP_XOR || dtype < DT_I32 || dtype > DT_U64) return -2;
+    for (int64_t h = 1; h < nheads; ++h)
+        if (heads[h] < heads[h - 1]) return -3;
+    static longacc acc; /* large; kept off the stack (oracle is single-threaded) */
+    scan_state st;
+    memset(&st, 0, sizeof st);
+    st.op = op;
+    st.dtype = dtype;
+    st.as_int = !is_float_dtype(dtype) || op == OP_AND || op == OP_OR || op == OP_XOR;
+    st.width = (dtype == DT_F64 || dtype == DT_I64 || dtype == DT_U64) ? 64
+             : (dtype == DT_F16 || dtype == DT_BF16) ? 16 : 32;
+    st.is_signed = (dtype == DT_I32 || dtype == DT_I64);
+    st.sum = &acc;
+    int64_t h = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int start = (i == 0);
+        while (h < nheads && heads[h] <= i) start |= (heads[h++] == i);
+        if (start) scan_restart(&st);
+        if (exclusive) scan_emit(&st, out, i);
+        scan_fold(&st, x, i);
+        if (!exclusive) scan_emit(&st, out, i);
     }
     return 0;
 }

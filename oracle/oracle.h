@@ -71,6 +71,18 @@ int orc_minmax(const void* x, int64_t n, int dtype, int is_max, double* out, int
 int orc_segmented(const void* x, const int64_t* offsets, int64_t nseg, int dtype, int op,
                   void* out);
 
+/* Scan, the prefix form of the reduction: out[i] is the reduction of the
+ * elements of i's run up to and including i (exclusive = 0), or of those
+ * strictly before i (exclusive != 0; the neutral element at a run's first
+ * position).  Position 0 and every position in heads[0..nheads) start a run
+ * (heads nondecreasing, values outside [0, n) ignored): no heads gives the
+ * plain scan, CSR segment offsets give the per-segment scan.  Results per
+ * position follow orc_segmented: double (exact-then-rounded sums, double-double
+ * products, exact min/max) for float data, uint64 bit patterns otherwise.
+ * out must hold n 8-byte entries. */
+int orc_scan(const void* x, int64_t n, int dtype, int op, int exclusive, const int64_t* heads,
+             int64_t nheads, void* out);
+
 /* Row-wise reduction of a float32 matrix [rows, cols] (row-major), op in
  * {sum, product, min, max}: y[r] as double (exact sum for sum), idx[r] the
  * lowest column attaining min/max (-1 otherwise), zeros[r] the number of

@@ -474,3 +474,140 @@ def test_segmented_int64_vs_python():
     out = oracle.segmented(x, off, "sum", "int64")
     for s in range(100):
         assert int(out[s]) == sum(int(v) for v in x[off[s]:off[s + 1]]) % M64
+
+
+# ---------------------------------------------------------------- scans
+# The scan is the prefix form of the reduction: out[i] reduces x[0..i]
+# (inclusive) or x[0..i) (exclusive), restarting at segment heads.
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 4097, 100_003])
+def test_scan_int_sum_closed_form(n):
+    # prefix sums of 1..n are k(k+1)/2 (mod 2^32); the exclusive form is shifted by one
+    x = np.arange(1, n + 1, dtype=np.uint64).astype(np.uint32)
+    k = np.arange(1, n + 1, dtype=np.uint64)
+    inc = oracle.scan(x, "sum", "uint32")
+    exc = oracle.scan(x, "sum", "uint32", exclusive=True)
+    assert np.array_equal(inc, (k * (k + 1) // 2) % M32)
+    assert np.array_equal(exc, ((k - 1) * k // 2) % M32)
+
+
+def test_scan_xor_closed_form():
+    n = 5000
+    x = np.arange(n, dtype=np.uint32)
+    inc = oracle.scan(x, "xor", "uint32")
+    assert [int(v) for v in inc] == [_xor_prefix(i) for i in range(n)]
+    exc = oracle.scan(x, "xor", "uint32", exclusive=True)
+    assert [int(v) for v in exc] == [_xor_prefix(i - 1) for i in range(n)]
+
+
+@pytest.mark.parametrize("dtype", ["int32", "uint32", "int64", "uint64"])
+def test_scan_int_vs_numpy_accumulate(dtype):
+    # numpy's cumulative sum / product / extrema / bitwise accumulations, with
+    # Python integers reducing modulo the width for + and x
+    rng = np.random.default_rng(11)
+    width = 32 if "32" in dtype else 64
+    signed = dtype.startswith("int")
+    n = 3000
+    x = rng.integers(-1000 if signed else 0, 1000, size=n, endpoint=True).astype(dtype)
+    bits = x.view(np.uint32 if width == 32 else np.uint64).astype(np.uint64)
+    mask = (1 << width) - 1
+    ref_sum = np.array([v & mask for v in np.cumsum([int(v) for v in x], dtype=object)], dtype=np.uint64)
+    assert np.array_equal(oracle.scan(x, "sum", dtype), ref_sum)
+    ref_max = np.maximum.accumulate(x).view(bits.dtype if width == 64 else np.uint32).astype(np.uint64)
+    ref_min = np.minimum.accumulate(x).view(bits.dtype if width == 64 else np.uint32).astype(np.uint64)
+    assert np.array_equal(oracle.scan(x, "max", dtype), ref_max)
+    assert np.array_equal(oracle.scan(x, "min", dtype), ref_min)
+    for op, uf in (("and", np.bitwise_and), ("or", np.bitwise_or), ("xor", np.bitwise_xor)):
+        assert np.array_equal(oracle.scan(x, op, dtype), uf.accumulate(bits)), op
+    odd = (rng.integers(0, 1 << 30, size=200) * 2 + 1).astype(dtype)
+    run, ref = 1, []
+    for v in odd:
+        run = (run * int(v)) & mask
+        ref.append(run)
+    assert np.array_equal(oracle.scan(odd, "prod", dtype), np.array(ref, dtype=np.uint64))
+
+
+def test_scan_paper_example_exact():
+    # Section 1.1's example: 1.5 + 4^50 - 4^50.  The exact prefix sums are 1.5,
+    # 4^50 + 1.5 (which rounds to 4^50) and 1.5, not the 0 a double fold gives.
+    x = np.array([1.5, 4.0 ** 50, -(4.0 ** 50)])
+    assert list(oracle.scan(x, "sum", "float64")) == [1.5, 4.0 ** 50, 1.5]
+    assert list(oracle.scan(x, "sum", "float64", exclusive=True)) == [0.0, 1.5, 4.0 ** 50]
+
+
+def test_scan_float_sum_vs_fsum_prefixes():
+    rng = np.random.default_rng(12)
+    x = (rng.uniform(-1, 1, 2000) * np.exp2(rng.integers(-30, 30, 2000))).astype(np.float32)
+    out = oracle.scan(x, "sum", "float32")
+    xs = [float(v) for v in x]
+    for i in list(range(0, 2000, 97)) + [1999]:
+        assert out[i] == math.fsum(xs[: i + 1]), i
+    exc = oracle.scan(x, "sum", "float32", exclusive=True)
+    assert exc[0] == 0.0 and all(exc[i] == math.fsum(xs[:i]) for i in range(1, 2000, 131))
+
+
+def test_scan_float_prod_and_minmax():
+    # powers of two multiply exactly; running extrema match numpy's accumulate
+    rng = np.random.default_rng(13)
+    k = rng.integers(-3, 4, size=300)
+    x = np.exp2(k).astype(np.float32)
+    assert np.array_equal(oracle.scan(x, "prod", "float32"), np.exp2(np.cumsum(k)).astype(np.float64))
+    y = rng.standard_normal(500).astype(np.float32)
+    assert np.array_equal(oracle.scan(y, "max", "float32"), np.maximum.accumulate(y).astype(np.float64))
+    assert np.array_equal(oracle.scan(y, "min", "float32", exclusive=True)[1:],
+                          np.minimum.accumulate(y)[:-1].astype(np.float64))
+    assert oracle.scan(y, "min", "float32", exclusive=True)[0] == math.inf
+    # a NaN makes every later running extreme NaN (IEEE 754-2019 maximum)
+    y[200] = np.nan
+    m = oracle.scan(y, "max", "float32")
+    assert not np.isnan(m[:200]).any() and np.isnan(m[200:]).all()
+
+
+def test_scan_half_dtypes_vs_numpy_decoding():
+    rng = np.random.default_rng(14)
+    h = rng.standard_normal(400).astype(np.float16)
+    vals = h.astype(np.float64)
+    assert np.array_equal(oracle.scan(h, "max", "float16"), np.maximum.accumulate(vals))
+    out = oracle.scan(h, "sum", "float16")
+    assert out[-1] == math.fsum(vals.tolist())
+    b = (rng.standard_normal(400).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    bvals = (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    assert np.array_equal(oracle.scan(b, "min", "bfloat16"), np.minimum.accumulate(bvals))
+
+
+def test_scan_segments_position_in_segment():
+    # x = all ones: the inclusive sum at i is i - head(i) + 1, the exclusive one
+    # i - head(i), where head(i) is the last run start <= i (position 0 counts)
+    rng = np.random.default_rng(15)
+    n = 5000
+    heads = np.sort(rng.choice(np.arange(-5, n + 5), size=300))
+    heads = np.concatenate([heads, heads[:20]])  # duplicates: empty segments
+    heads.sort()
+    inc = oracle.scan(np.ones(n, np.int32), "sum", "int32", heads=heads)
+    exc = oracle.scan(np.ones(n, np.int32), "sum", "int32", exclusive=True, heads=heads)
+    starts = sorted({0} | {int(h) for h in heads if 0 <= h < n})
+    last = np.zeros(n, np.int64)
+    for s in starts:
+        last[s:] = s
+    pos = np.arange(n) - last
+    assert np.array_equal(inc, pos + 1) and np.array_equal(exc, pos)
+
+
+def test_scan_segments_end_values_match_segment_reduction():
+    # the last inclusive value of each nonempty segment is that segment's
+    # reduction (computed by the separate segmented fold)
+    rng = np.random.default_rng(16)
+    lengths = rng.integers(0, 50, size=200)
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    x = rng.integers(-2**31, 2**31, size=int(off[-1])).astype(np.int32)
+    for op in ("sum", "max", "xor"):
+        inc = oracle.scan(x, op, "int32", heads=off)
+        red = oracle.segmented(x, off, op, "int32")
+        for s in range(200):
+            if lengths[s]:
+                assert inc[off[s + 1] - 1] == red[s]
+
+
+def test_scan_rejects_decreasing_heads():
+    with pytest.raises(ValueError):
+        oracle.scan(np.ones(10, np.int32), "sum", "int32", heads=np.array([5, 2]))
