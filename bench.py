@@ -211,11 +211,60 @@ def bench_rowwise(rd, torch, steps, warmup, plain_s_per_byte):
     return res
 
 
+def bench_scan(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
+    """Inclusive float32 sum scan at n = 2^28 (reads 1 GiB, writes 1 GiB), its
+    segmented form over the log-normal segments, and torch.cumsum beside it."""
+    dev = torch.device("cuda")
+    n = 2 ** 28
+    x_np = W.plain(n, "float32", "sum", config=1, salt=7)
+    x = torch.from_numpy(x_np).to(dev)
+    out = torch.empty_like(x)
+    t = time_launches(lambda: rd.scan(x, "sum", out=out), steps, warmup, torch)
+    nbytes = 8 * n
+    res = {"n": n, "ms": round(t * 1e3, 4), "GBps": round(gbps(nbytes, t), 1),
+           "per_byte_vs_plain": round((t / nbytes) / plain_s_per_byte, 4),
+           "config": rd.config_get("scan", torch.float32, "sum", n)}
+    worst = 0.0
+    for i in (4095, (1 << 27) + 12_345, n - 1):
+        ref, asum = oracle.exact_sum(x_np[: i + 1])
+        worst = max(worst, abs(float(out[i].item()) - ref) / asum)
+    res["sampled_err_over_abs_sum"] = worst
+    res["pass"] = worst <= 32 * 2.0 ** -24
+    tc = time_launches(lambda: torch.cumsum(x, 0, out=out), steps, warmup, torch)
+    res["torch_cumsum_ms"] = round(tc * 1e3, 4)
+    res["torch_cumsum_GBps"] = round(gbps(nbytes, tc), 1)
+    del x, out
+    torch.cuda.empty_cache()
+    lens = W.segment_lengths()
+    off_np = W.offsets_from_lengths(lens)
+    m = int(off_np[-1])
+    xs_np = W.segmented_values(m, "sum")
+    xs = torch.from_numpy(xs_np).to(dev)
+    offs = torch.from_numpy(off_np).to(dev)
+    outs = torch.empty_like(xs)
+    ts = time_launches(lambda: rd.scan(xs, "sum", out=outs, offsets=offs), steps, warmup, torch)
+    sbytes = 8 * m + 8 * off_np.size
+    seg = {"segments": int(lens.size), "elements": m, "ms": round(ts * 1e3, 4), "GBps": round(gbps(sbytes, ts), 1),
+           "per_byte_vs_plain": round((ts / sbytes) / plain_s_per_byte, 4)}
+    worst = 0.0
+    for s_ in (0, 1, lens.size // 2, lens.size - 1):
+        a, b = int(off_np[s_]), int(off_np[s_ + 1])
+        if b > a:
+            ref, asum = oracle.exact_sum(xs_np[a:b])
+            worst = max(worst, abs(float(outs[b - 1].item()) - ref) / max(asum, 1e-300))
+    seg["sampled_err_over_abs_sum"] = worst
+    seg["pass"] = worst <= 32 * 2.0 ** -24
+    res["segmented"] = seg
+    del xs, outs, offs
+    torch.cuda.empty_cache()
+    return res
+
+
 # ---------------------------------------------------------------- HBM traffic
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_reduce_kernel_f32_sum_2p28.txt")
 KERNEL_SOURCES = ["paper_1710_07358_amd/csrc/rd_device.hpp", "paper_1710_07358_amd/csrc/reduce_plain.hpp",
-                  "paper_1710_07358_amd/csrc/rd_internal.hpp", "paper_1710_07358_amd/csrc/k_f32_plain.hip"]
+                  "paper_1710_07358_amd/csrc/k_f32_plain.hip"]
 
 
 def kernel_fingerprint(launch: dict) -> str:
@@ -369,6 +418,8 @@ def main() -> int:
                                                  args.warmup, plain_spb)
         log("row-wise forward + backward")
         secondary["rowwise"] = bench_rowwise(rd, torch, max(args.steps // 5, 3), 2, plain_spb)
+        log("scan")
+        secondary["scan"] = bench_scan(rd, W, oracle, torch, np, max(args.steps // 5, 5), 2, plain_spb)
         if not args.no_precision:
             log("precision sets")
             secondary["precision"] = bench_precision(rd, W, oracle, torch, n)

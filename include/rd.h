@@ -90,10 +90,13 @@ typedef struct rd_config {
  * fixed at 256, `unroll` is the number of 4-column stripes each work-item
  * handles per step (1, 2, 4 or 8; 16 is treated as 8), `blocks_per_cu` sizes
  * the persistent grid over rows, and `nontemporal` applies to the forward's
- * loads and the backward's stores. */
+ * loads and the backward's stores.  For scans (RD_KIND_SCAN) `block` and
+ * `blocks_per_cu` size the tiles (block x 4 x 16 bytes) and the persistent
+ * grid, `nontemporal` applies to loads and stores, and `unroll` and `layout`
+ * are ignored. */
 typedef enum rd_kind {
     RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2, RD_KIND_ROWWISE = 3,
-    RD_KIND_ROWWISE_BWD = 4
+    RD_KIND_ROWWISE_BWD = 4, RD_KIND_SCAN = 5
 } rd_kind;
 
 /* ---- library and workspace management ---------------------------------- */
@@ -180,6 +183,43 @@ rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int vari
  * [offsets[0], offsets[nseg]). */
 rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nseg, rd_dtype dt,
                               rd_op op, void* out, rd_workspace* ws, void* stream);
+
+/* ---- scan ---------------------------------------------------------------- */
+
+/* Inclusive (exclusive = 0) or exclusive (exclusive != 0) scan, the prefix
+ * form of the reduction of Section 1.1 (the primitive behind the counting
+ * sort, stream compaction and radix sort the Introduction names):
+ *   inclusive: out[i] = x[0] (+) ... (+) x[i]
+ *   exclusive: out[i] = x[0] (+) ... (+) x[i-1], out[0] = the neutral element
+ *   x   : device array of n elements of dtype dt (element-aligned)
+ *   out : device array of n elements of rd_out_dtype(dt, op); it may be x
+ *         itself when the output dtype has x's element size, and must not
+ *         otherwise overlap x
+ *   n   : 0 <= n <= 2^19 tiles of block x 4 x 16 bytes (2^31 float32 elements
+ *         with 256-wide work-groups); more gives RD_ERR_INVALID_ARG
+ * One pass and one launch: x is read once and out written once.  Each tile
+ * publishes its aggregate and folds its prefix from earlier aggregates in a
+ * fixed tree (groups of 64 tiles, groups of 64 groups, ...), so float results
+ * are the same on every run.  float32 sums carry prefixes across tiles in
+ * float64; float products accumulate in float64 as in rd_reduce.  Capturable
+ * in a HIP graph (no host synchronisation, no allocation with ws != NULL). */
+rd_status rd_scan(const void* x, int64_t n, rd_dtype dt, rd_op op, int exclusive, void* out,
+                  rd_workspace* ws, void* stream);
+
+/* Scan restarted at every segment start.  With the CSR offsets of nseg
+ * segments (noffsets = nseg + 1 non-decreasing entries, offsets[0] = 0,
+ * offsets[nseg] = n), out[i] for offsets[s] <= i < offsets[s+1] reduces
+ * x[offsets[s] .. i] (inclusive) or x[offsets[s] .. i) (exclusive; the neutral
+ * element at a segment's first position).  In general position 0 and every
+ * offset in [0, n) start a run, so elements before offsets[0] or from
+ * offsets[nseg] on are scanned as runs of their own, and empty segments
+ * change nothing.  Decreasing offsets give unspecified values but no access
+ * outside x, out and offsets.
+ *   offsets  : device int64 array of noffsets entries, noffsets < 2^31
+ * Adds one small launch that finds, per tile, its first run start. */
+rd_status rd_segmented_scan(const void* x, int64_t n, const int64_t* offsets, int64_t noffsets,
+                            rd_dtype dt, rd_op op, int exclusive, void* out, rd_workspace* ws,
+                            void* stream);
 
 /* ---- row-wise reduction and its gradient --------------------------------- */
 

@@ -4,7 +4,7 @@ behind the C ABI of include/rd.h, bound here for PyTorch tensors.
 The binding is imported on first use, so ``paper_1710_07358_amd.workloads``
 (seeded inputs) works without the built library.
 """
-_API = ("reduce", "reduce_compensated", "argreduce", "reduce_paper_design", "segmented", "rowreduce", "rowreduce_forward",
+_API = ("reduce", "reduce_compensated", "argreduce", "reduce_paper_design", "segmented", "scan", "rowreduce", "rowreduce_forward",
         "rowreduce_backward", "RowReduce", "Workspace", "out_dtype", "saved_bytes",
         "config_get", "config_force", "tune_load", "DTYPES", "OPS")
 

@@ -19,7 +19,7 @@ RD_I32, RD_U32, RD_F32, RD_F64, RD_F16, RD_BF16, RD_I64, RD_U64 = range(8)
 RD_SUM, RD_PROD, RD_MIN, RD_MAX, RD_AND, RD_OR, RD_XOR = range(7)
 RD_OK, RD_ERR_INVALID_ARG, RD_ERR_UNSUPPORTED, RD_ERR_HIP, RD_ERR_NOMEM, RD_ERR_CAPTURE, RD_ERR_WORKSPACE = (
     0, -1, -2, -3, -4, -5, -6)
-RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD = range(5)
+RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD, RD_KIND_SCAN = range(6)
 
 STATUS_NAMES = {0: "RD_OK", -1: "RD_ERR_INVALID_ARG", -2: "RD_ERR_UNSUPPORTED", -3: "RD_ERR_HIP",
                 -4: "RD_ERR_NOMEM", -5: "RD_ERR_CAPTURE", -6: "RD_ERR_WORKSPACE"}
@@ -46,6 +46,8 @@ SIGNATURES = {
     "rd_segmented_reduce": (_ci, [_vp, _vp, _i64, _ci, _ci, _vp, _vp, _vp]),
     "rd_reduce_paper_design": (_ci, [_vp, _i64, _ci, _ci, _ci, _vp, _vp, _vp]),
     "rd_argreduce": (_ci, [_vp, _i64, _ci, _ci, _vp, _vp, _vp, _vp]),
+    "rd_scan": (_ci, [_vp, _i64, _ci, _ci, _ci, _vp, _vp, _vp]),
+    "rd_segmented_scan": (_ci, [_vp, _i64, _vp, _i64, _ci, _ci, _ci, _vp, _vp, _vp]),
     "rd_saved_bytes": (_sz, [_ci, _i64, _i64]),
     "rd_rowreduce_fwd": (_ci, [_vp, _i64, _i64, _ci, _ci, _vp, _vp, _vp]),
     "rd_rowreduce_bwd": (_ci, [_vp, _vp, _vp, _i64, _i64, _ci, _ci, _vp, _vp]),

@@ -21,7 +21,7 @@ OPS = {"sum": N.RD_SUM, "prod": N.RD_PROD, "min": N.RD_MIN, "max": N.RD_MAX,
        "and": N.RD_AND, "or": N.RD_OR, "xor": N.RD_XOR}
 KINDS = {"plain": N.RD_KIND_PLAIN, "compensated": N.RD_KIND_COMPENSATED,
          "segmented": N.RD_KIND_SEGMENTED, "rowwise": N.RD_KIND_ROWWISE,
-         "rowwise_bwd": N.RD_KIND_ROWWISE_BWD}
+         "rowwise_bwd": N.RD_KIND_ROWWISE_BWD, "scan": N.RD_KIND_SCAN}
 
 
 def _dt(t: torch.Tensor) -> int:
@@ -165,6 +165,36 @@ def segmented(x: torch.Tensor, offsets: torch.Tensor, op: str, out: torch.Tensor
     with torch.cuda.device(x.device):
         N.check(N.lib().rd_segmented_reduce(x.data_ptr(), offsets.data_ptr(), nseg, _dt(x), _op(op),
                                             out.data_ptr(), _ws(workspace), _stream(x.device)))
+    return out
+
+
+def scan(x: torch.Tensor, op: str, exclusive: bool = False, out: torch.Tensor | None = None,
+         offsets: torch.Tensor | None = None, workspace: Workspace | None = None) -> torch.Tensor:
+    """Inclusive (or exclusive) scan of a contiguous device tensor, one pass.
+
+    out[i] = x[0] (op) ... (op) x[i] (exclusive: up to x[i-1]).  With CSR
+    ``offsets`` (int64, nseg + 1 entries) the scan restarts at every segment
+    start.  ``out`` may be ``x`` when the output dtype equals x's dtype."""
+    x = _dev_tensor(x, "x")
+    odt = out_dtype(x.dtype, op)
+    if out is None:
+        out = torch.empty(x.shape, dtype=odt, device=x.device)
+    elif out.dtype != odt or out.numel() != x.numel() or not out.is_cuda or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {odt} GPU tensor of {x.numel()} elements")
+    if x.numel() == 0:
+        return out
+    with torch.cuda.device(x.device):
+        if offsets is None:
+            N.check(N.lib().rd_scan(x.data_ptr(), x.numel(), _dt(x), _op(op), int(bool(exclusive)),
+                                    out.data_ptr(), _ws(workspace), _stream(x.device)))
+        else:
+            offsets = _dev_tensor(offsets, "offsets")
+            if offsets.dtype != torch.int64 or offsets.dim() != 1:
+                raise ValueError("offsets must be a 1-D int64 tensor")
+            N.check(N.lib().rd_segmented_scan(x.data_ptr(), x.numel(),
+                                              offsets.data_ptr() if offsets.numel() else None,
+                                              offsets.numel(), _dt(x), _op(op), int(bool(exclusive)),
+                                              out.data_ptr(), _ws(workspace), _stream(x.device)))
     return out
 
 

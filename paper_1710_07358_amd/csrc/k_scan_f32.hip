@@ -1,0 +1,18 @@
+// k_scan_f32.hip -- instantiations of the scan kernels: float32.
+#include "scan.hpp"
+
+namespace rd {
+
+template <bool SEG> ScanFn scan_f32_ops(rd_op op, bool nt) {
+  switch (op) {
+    case RD_SUM: return scan_pick<Store::F32, Op::Sum, SEG>(nt);
+    case RD_PROD: return scan_pick<Store::F32, Op::Prod, SEG>(nt);
+    case RD_MIN: return scan_pick<Store::F32, Op::Min, SEG>(nt);
+    case RD_MAX: return scan_pick<Store::F32, Op::Max, SEG>(nt);
+    default: return nullptr;  // bitwise: the 32-bit pattern kernels
+  }
+}
+
+ScanFn scan_f32(rd_op op, bool seg, bool nt) { return seg ? scan_f32_ops<true>(op, nt) : scan_f32_ops<false>(op, nt); }
+
+}  // namespace rd

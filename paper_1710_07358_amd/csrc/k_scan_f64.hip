@@ -1,0 +1,18 @@
+// k_scan_f64.hip -- instantiations of the scan kernels: float64.
+#include "scan.hpp"
+
+namespace rd {
+
+template <bool SEG> ScanFn scan_f64_ops(rd_op op, bool nt) {
+  switch (op) {
+    case RD_SUM: return scan_pick<Store::F64, Op::Sum, SEG>(nt);
+    case RD_PROD: return scan_pick<Store::F64, Op::Prod, SEG>(nt);
+    case RD_MIN: return scan_pick<Store::F64, Op::Min, SEG>(nt);
+    case RD_MAX: return scan_pick<Store::F64, Op::Max, SEG>(nt);
+    default: return nullptr;  // bitwise: the 64-bit pattern kernels
+  }
+}
+
+ScanFn scan_f64(rd_op op, bool seg, bool nt) { return seg ? scan_f64_ops<true>(op, nt) : scan_f64_ops<false>(op, nt); }
+
+}  // namespace rd

@@ -80,7 +80,14 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t counters_bytes() { return round_up(kAlign + (size_t)rd::kMaxSegWaves * 4, kAlign); }
 size_t partial_bytes() { return round_up((size_t)rd::kMaxGrid * rd::kPartialWords * 8, kAlign); }
 size_t carry_bytes() { return round_up((size_t)rd::kMaxSegWaves * 2 * rd::kCarryWords * 8, kAlign); }
-size_t workspace_bytes() { return counters_bytes() + partial_bytes() + carry_bytes() + (size_t)rd::kDesignBytes; }
+// Scans: control words, per-tile first-head words, tagged slots.
+size_t scan_bytes() {
+  return kAlign + round_up((size_t)rd::kScanTiles * 8, kAlign) +
+         round_up((size_t)rd::kScanSlots * rd::kScanSlotWords * 8, kAlign);
+}
+size_t workspace_bytes() {
+  return counters_bytes() + partial_bytes() + carry_bytes() + (size_t)rd::kDesignBytes + scan_bytes();
+}
 
 rd_status create_workspace(rd_workspace** out, int device) {
   int prev = -1;
@@ -112,6 +119,12 @@ rd_status create_workspace(rd_workspace** out, int device) {
   s.carry_cap = (int64_t)rd::kMaxSegWaves * 2;
   p += carry_bytes();
   s.design = p;
+  p += rd::kDesignBytes;
+  s.scan_ctl = (unsigned*)p;
+  p += kAlign;
+  s.scan_tile_first = (uint64_t*)p;
+  p += round_up((size_t)rd::kScanTiles * 8, kAlign);
+  s.scan_slots = (uint64_t*)p;
   *out = ws;
   return RD_OK;
 }
@@ -183,12 +196,14 @@ std::vector<TuneEntry> builtin_table() {
   t.push_back({RD_KIND_ROWWISE, 4, 1, 0, 62, {256, 1, 8, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 0, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 0, 0}});
+  for (int es : {2, 4, 8})
+    for (int oc = 0; oc < 3; ++oc) t.push_back({RD_KIND_SCAN, es, oc, 0, 62, {256, 4, 4, 1, 0}});
   return t;
 }
 
 std::vector<TuneEntry> g_table = builtin_table();
-constexpr int kKinds = 5;
-bool g_forced[kKinds] = {false, false, false, false, false};
+constexpr int kKinds = 6;
+bool g_forced[kKinds] = {false, false, false, false, false, false};
 rd_config g_force_cfg[kKinds];
 
 int log2_ceil(int64_t n) {
@@ -279,7 +294,61 @@ SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
   return nullptr;
 }
 
+ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, bool nt) {
+  const bool bitwise = (op == RD_AND || op == RD_OR || op == RD_XOR);
+  switch (dt) {
+    case RD_I32:
+    case RD_U32: return scan_int(dt, op, seg, nt);
+    case RD_F32: return bitwise ? scan_int(RD_U32, op, seg, nt) : scan_f32(op, seg, nt);
+    case RD_F64: return bitwise ? scan_int64(RD_U64, op, seg, nt) : scan_f64(op, seg, nt);
+    case RD_F16:
+    case RD_BF16: return scan_half(dt, op, seg, nt);
+    case RD_I64:
+    case RD_U64: return scan_int64(dt, op, seg, nt);
+  }
+  return nullptr;
+}
+
 }  // namespace rd
+
+namespace {
+
+// Shared body of rd_scan and rd_segmented_scan.
+rd_status scan_call(const char* name, const void* x, int64_t n, const int64_t* heads, int64_t nheads, bool seg,
+                    rd_dtype dt, rd_op op, int exclusive, void* out, rd_workspace* ws, void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "%s: invalid dtype %d", name, (int)dt);
+  if (!valid_op(op)) return fail(RD_ERR_INVALID_ARG, "%s: invalid op %d", name, (int)op);
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "%s: n = %lld < 0", name, (long long)n);
+  if (nheads < 0 || nheads >= ((int64_t)1 << 31))
+    return fail(RD_ERR_INVALID_ARG, "%s: noffsets = %lld outside [0, 2^31)", name, (long long)nheads);
+  if (n == 0) return RD_OK;
+  const size_t es = rd_dtype_size(dt);
+  rd_dtype odt;
+  rd_out_dtype(dt, op, &odt);
+  rd_status st;
+  if ((st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(out, rd_dtype_size(odt), "out")) != RD_OK) return st;
+  if (seg && nheads > 0 && (st = check_ptr(heads, 8, "offsets")) != RD_OK) return st;
+  int dev;
+  DeviceInfo info;
+  if ((st = current_device(&dev, &info)) != RD_OK) return st;
+  rd_workspace* w;
+  if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
+  const rd_config cfg = choose_config(RD_KIND_SCAN, dt, op, n);
+  const int64_t tile = (int64_t)cfg.block * rd::kScanUnroll * (int64_t)(16 / es);
+  const int64_t ntiles = (n + tile - 1) / tile;
+  if (ntiles > rd::kScanTiles)
+    return fail(RD_ERR_INVALID_ARG, "%s: n = %lld needs %lld tiles of %lld elements; at most %lld per call", name,
+                (long long)n, (long long)ntiles, (long long)tile, (long long)rd::kScanTiles);
+  rd::ScanFn fn = rd::scan_launcher(dt, op, seg, cfg.nontemporal != 0);
+  if (!fn) return fail(RD_ERR_UNSUPPORTED, "%s: no kernel for dtype %d op %d", name, (int)dt, (int)op);
+  const rd::Launch l{cfg.block, std::max(1, cfg.blocks_per_cu * info.cus), rd::kScanUnroll, cfg.nontemporal != 0, 0};
+  const rd::ScanCall c{x, n, out, exclusive != 0, seg ? heads : nullptr, seg ? nheads : 0};
+  hipError_t e = fn(c, w->scratch, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, name);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -451,6 +520,16 @@ rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int vari
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce_paper_design launch");
 }
 
+rd_status rd_scan(const void* x, int64_t n, rd_dtype dt, rd_op op, int exclusive, void* out, rd_workspace* ws,
+                  void* stream) {
+  return scan_call("rd_scan", x, n, nullptr, 0, false, dt, op, exclusive, out, ws, stream);
+}
+
+rd_status rd_segmented_scan(const void* x, int64_t n, const int64_t* offsets, int64_t noffsets, rd_dtype dt,
+                            rd_op op, int exclusive, void* out, rd_workspace* ws, void* stream) {
+  return scan_call("rd_segmented_scan", x, n, offsets, noffsets, true, dt, op, exclusive, out, ws, stream);
+}
+
 size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
   if (rows < 0 || cols < 0) return 0;
   return rd::rowreduce_saved_bytes(op, rows, cols);
@@ -499,14 +578,14 @@ rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int6
 }
 
 rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_config* cfg) {
-  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_ROWWISE_BWD || !valid_dtype(dt) || !valid_op(op))
+  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_SCAN || !valid_dtype(dt) || !valid_op(op))
     return fail(RD_ERR_INVALID_ARG, "rd_config_get: bad argument");
   *cfg = choose_config(kind, dt, op, n);
   return RD_OK;
 }
 
 rd_status rd_config_force(rd_kind kind, const rd_config* cfg) {
-  if (kind < RD_KIND_PLAIN || kind > RD_KIND_ROWWISE_BWD) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
+  if (kind < RD_KIND_PLAIN || kind > RD_KIND_SCAN) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
   if (cfg && !valid_config(*cfg))
     return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d layout %d",
                 cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal, cfg->layout);

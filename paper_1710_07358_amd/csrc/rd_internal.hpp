@@ -30,7 +30,30 @@ struct Scratch {
   int64_t partial_cap;  // work-groups
   int64_t carry_cap;    // carry slots
   void* design;         // paper-design baselines: plain partials (kDesignBytes)
+  // Scans: control words, per-tile first-head index, published tile and
+  // group aggregates (tagged with a launch epoch, so never cleared).
+  unsigned* scan_ctl;         // [0] epoch, [1] next tile, [2] arrivals, [3] status
+  uint64_t* scan_tile_first;  // kScanTiles words
+  uint64_t* scan_slots;       // kScanSlots x kScanSlotWords words
 };
+
+// Scan tiles per call (block x U x V elements each), tree levels (groups
+// of 64), words per published slot, epoch range, 16-byte loads per lane
+// and piece.
+constexpr int64_t kScanTiles = 1 << 19;
+constexpr int kScanLevels = 4;
+constexpr int kScanSlotWords = 2;
+constexpr unsigned kScanEpochs = 0x7FFFFFFFu;
+constexpr int kScanUnroll = 4;
+constexpr int64_t scan_slots_total() {
+  int64_t total = 0, cap = kScanTiles;
+  for (int l = 0; l < kScanLevels; ++l) {
+    total += cap;
+    cap = (cap + 63) / 64;
+  }
+  return total;
+}
+constexpr int64_t kScanSlots = scan_slots_total();
 
 constexpr int64_t kDesignBytes = 256 * 1024;
 
@@ -47,6 +70,24 @@ using SegFn = hipError_t (*)(const void* x, const int64_t* offsets, int64_t nseg
                              const Scratch& ws, const Launch& l, hipStream_t s);
 using ArgFn = hipError_t (*)(const void* x, int64_t n, void* value_out, int64_t* index_out,
                              const Scratch& ws, const Launch& l, hipStream_t s);
+
+struct ScanCall {
+  const void* x;
+  int64_t n;
+  void* out;
+  bool exclusive;
+  const int64_t* heads;  // segmented form: run starts, else null
+  int64_t nheads;
+};
+using ScanFn = hipError_t (*)(const ScanCall& c, const Scratch& ws, const Launch& l, hipStream_t s);
+
+// Scan kernels (plain when seg is false).  nullptr when (dt, op) is not offered.
+ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, bool nontemporal);
+ScanFn scan_int(rd_dtype dt, rd_op op, bool seg, bool nt);    // RD_I32 / RD_U32, 32-bit bitwise
+ScanFn scan_f32(rd_op op, bool seg, bool nt);
+ScanFn scan_f64(rd_op op, bool seg, bool nt);                 // also 64-bit bitwise of float64
+ScanFn scan_int64(rd_dtype dt, rd_op op, bool seg, bool nt);  // RD_I64 / RD_U64
+ScanFn scan_half(rd_dtype dt, rd_op op, bool seg, bool nt);   // RD_F16 / RD_BF16, 16-bit bitwise
 
 // Arg-reduction (min/max with the lowest index); unroll 2, 4 or 8.
 ArgFn arg_launcher(rd_dtype dt, bool is_max, int unroll, bool nontemporal);

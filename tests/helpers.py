@@ -89,3 +89,24 @@ def check_against_oracle(gpu_out: torch.Tensor, ref, x: np.ndarray, op: str, dty
             assert abs(got - ref) <= bound * abs(ref), f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
     else:
         raise ValueError(op)
+
+
+def as_oracle_array(out: torch.Tensor, dtype: str, op: str) -> np.ndarray:
+    """GPU results in the oracle's array representation: uint64 bit patterns
+    for integer dtypes and bitwise ops, float64 values otherwise."""
+    o = out.detach().reshape(-1).cpu()
+    if dtype in INTS or op in BITWISE:
+        size = o.element_size()
+        view = {2: torch.int16, 4: torch.int32, 8: torch.int64}[size]
+        v = o.view(view).numpy()
+        if size < 8:
+            return (v.astype(np.int64) % (1 << (8 * size))).astype(np.uint64)
+        return v.view(np.uint64)
+    return o.to(torch.float64).numpy()
+
+
+def abs_storage(x: np.ndarray, dtype: str) -> np.ndarray:
+    """|x| in x's storage (sign bit cleared; float16/bfloat16 are uint16 bits)."""
+    if dtype in ("float16", "bfloat16"):
+        return (x.view(np.uint16) & np.uint16(0x7FFF)).astype(np.uint16)
+    return np.abs(x)

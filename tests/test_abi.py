@@ -102,6 +102,17 @@ def test_host_errors_before_any_device_call(N):
     assert lib.rd_rowreduce_fwd(fake, 2, 2 ** 31, N.RD_F32, N.RD_MAX, fake, fake, None) == N.RD_ERR_INVALID_ARG
     assert lib.rd_rowreduce_fwd(fake, 2, 2, N.RD_F32, N.RD_MAX, fake, None, None) == N.RD_ERR_INVALID_ARG
     assert lib.rd_rowreduce_bwd(fake, fake, None, 2, 2, N.RD_F32, N.RD_PROD, fake, None) == N.RD_ERR_INVALID_ARG
+    # scans: validation happens on the host before any device call
+    assert lib.rd_scan(fake, -1, N.RD_F32, N.RD_SUM, 0, fake, None, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_scan(fake, 0, N.RD_F32, N.RD_SUM, 0, fake, None, None) == N.RD_OK  # nothing to do
+    assert lib.rd_scan(fake, 4, N.RD_F32, 9, 0, fake, None, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_scan(fake, 4, N.RD_F16, N.RD_SUM, 0, ctypes.c_void_p(0x10002), None, None) == N.RD_ERR_INVALID_ARG
+    assert b"out" in lib.rd_last_error()  # float16 sums write float32: 2-byte alignment is not enough
+    assert lib.rd_segmented_scan(fake, 8, fake, -1, N.RD_I32, N.RD_SUM, 0, fake, None, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_segmented_scan(fake, 8, fake, 1 << 31, N.RD_I32, N.RD_SUM, 0, fake, None,
+                                 None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_segmented_scan(fake, 8, ctypes.c_void_p(0x10004), 3, N.RD_I32, N.RD_SUM, 1, fake, None,
+                                 None) == N.RD_ERR_INVALID_ARG
     assert lib.rd_workspace_reset(None, None) == N.RD_ERR_INVALID_ARG
     assert lib.rd_workspace_destroy(None) == N.RD_OK
 
@@ -129,6 +140,9 @@ def test_config_force_and_tune_table(N, tmp_path):
     bad_layout = N.RdConfig(256, 4, 1, 0, 3)
     assert lib.rd_config_force(N.RD_KIND_PLAIN, ctypes.byref(bad_layout)) == N.RD_ERR_INVALID_ARG
     assert lib.rd_config_force(N.RD_KIND_PLAIN, None) == N.RD_OK
+    assert lib.rd_config_get(N.RD_KIND_SCAN, N.RD_F32, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
+    assert got.block % 64 == 0 and got.blocks_per_cu >= 1
+    assert lib.rd_config_force(N.RD_KIND_SCAN + 1, None) == N.RD_ERR_INVALID_ARG
     table = tmp_path / "tune.txt"
     table.write_text("# kind esize opclass lo hi block unroll bpc nt layout\n0 4 0 20 30 1024 4 2 1 1\n")
     assert lib.rd_tune_load(str(table).encode()) == N.RD_OK
