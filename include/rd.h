@@ -199,7 +199,7 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
  *         with 256-wide work-groups); more gives RD_ERR_INVALID_ARG
  * One pass and one launch: x is read once and out written once.  Each tile
  * publishes its aggregate and folds its prefix from earlier aggregates in a
- * fixed tree (groups of 64 tiles, groups of 64 groups, ...), so float results
+ * fixed tree (groups of 8 tiles, groups of 8 groups, ...), so float results
  * are the same on every run.  float32 sums carry prefixes across tiles in
  * float64; float products accumulate in float64 as in rd_reduce.  Capturable
  * in a HIP graph (no host synchronisation, no allocation with ws != NULL). */

@@ -196,8 +196,10 @@ std::vector<TuneEntry> builtin_table() {
   t.push_back({RD_KIND_ROWWISE, 4, 1, 0, 62, {256, 1, 8, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 0, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 0, 0}});
+  // Scans, measured for float32 sums at n = 2^28: large tiles (one
+  // 1024-wide work-group per CU) keep the per-tile look-back cost small.
   for (int es : {2, 4, 8})
-    for (int oc = 0; oc < 3; ++oc) t.push_back({RD_KIND_SCAN, es, oc, 0, 62, {256, 4, 4, 1, 0}});
+    for (int oc = 0; oc < 3; ++oc) t.push_back({RD_KIND_SCAN, es, oc, 0, 62, {1024, 4, 1, 1, 0}});
   return t;
 }
 

@@ -37,22 +37,27 @@ struct Scratch {
   uint64_t* scan_slots;       // kScanSlots x kScanSlotWords words
 };
 
-// Scan tiles per call (block x U x V elements each), tree levels (groups
-// of 64), words per published slot, epoch range, 16-byte loads per lane
-// and piece.
+// Scan tiles per call (block x U x V elements each), fan-out and levels of
+// the tree of tile aggregates (kScanFan^kScanLevels >= kScanTiles), words
+// per published slot, epoch range, 16-byte loads per lane and piece.
 constexpr int64_t kScanTiles = 1 << 19;
-constexpr int kScanLevels = 4;
+constexpr int kScanFanLog = 3;
+constexpr int kScanFan = 1 << kScanFanLog;
+constexpr int kScanLevels = 7;
 constexpr int kScanSlotWords = 2;
 constexpr unsigned kScanEpochs = 0x7FFFFFFFu;
 constexpr int kScanUnroll = 4;
+// Slots: the group aggregates of every level.
 constexpr int64_t scan_slots_total() {
   int64_t total = 0, cap = kScanTiles;
   for (int l = 0; l < kScanLevels; ++l) {
     total += cap;
-    cap = (cap + 63) / 64;
+    cap = (cap + kScanFan - 1) / kScanFan;
   }
   return total;
 }
+static_assert(kScanLevels * kScanFan <= 64, "one wavefront reads every level at once");
+static_assert(((int64_t)1 << (kScanFanLog * kScanLevels)) >= kScanTiles, "tree covers every tile");
 constexpr int64_t kScanSlots = scan_slots_total();
 
 constexpr int64_t kDesignBytes = 256 * 1024;

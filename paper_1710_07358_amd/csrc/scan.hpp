@@ -15,7 +15,7 @@
 //
 // Across tiles (single pass: x is read once and out written once) every
 // tile publishes its aggregate, and a tile's exclusive prefix is folded from
-// aggregates in a FIXED tree: tiles form groups of 64, groups of 64 groups,
+// aggregates in a FIXED tree: tiles form groups of 8, groups of 8 groups,
 // and so on; the last tile of a complete group also publishes the group's
 // aggregate.  Tile t's prefix is the fold of its earlier siblings at every
 // level.  Because the tree does not depend on timing, float results are the
@@ -110,27 +110,21 @@ __device__ __forceinline__ void slot_put(uint64_t* slot, Item it, uint32_t tag) 
     __hip_atomic_store(slot + i, hi | (uint64_t)w.w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait for a slot of this launch.  The wait is bounded: a correct launch
-// never comes close, and once any wait has run out (status set) the others
-// stop waiting too, so a broken launch still ends promptly, with the status
-// word saying so.
+// Bound of a wait for published slots: a correct launch never comes
+// close, and once any wait has run out (status word set) the others stop
+// waiting too, so a broken launch still ends promptly, with the status word
+// saying so.
 constexpr int kScanSpin = 1 << 16;
 
-template <class Ch, class Item, class IS>
-__device__ __forceinline__ Item slot_wait(const uint64_t* slot, uint32_t tag, unsigned* status) {
-  constexpr int P = (int)(sizeof(Ch) / 4);
-  struct W { uint32_t w[P]; };
-  W w;
-  uint32_t f = 0;
+// Wait (in the lanes where `mine` holds) until every word of the slot at
+// src carries this launch's tag; w holds the words already loaded.
+template <int P>
+__device__ __forceinline__ void scan_wait(uint64_t (&w)[P], const uint64_t* src, bool mine, uint32_t tag,
+                                          unsigned* status) {
   for (int spin = 0;; ++spin) {
     bool ok = true;
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const uint64_t word = __hip_atomic_load(slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ok = ok && (uint32_t)(word >> 33) == tag;
-      w.w[i] = (uint32_t)word;
-      f = (uint32_t)(word >> 32) & 1u;
-    }
+    for (int i = 0; i < P; ++i) ok = ok && (!mine || (uint32_t)(w[i] >> 33) == tag);
     if (ok) break;
     if (spin >= kScanSpin) {
       __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -138,16 +132,20 @@ __device__ __forceinline__ Item slot_wait(const uint64_t* slot, uint32_t tag, un
     }
     if ((spin & 63) == 63 && __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
     __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (mine && (uint32_t)(w[i] >> 33) != tag)
+        w[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  return IS::with(__builtin_bit_cast(Ch, w), f);
 }
 
-// Slot index of group g at level l (groups of 64^l tiles).
+// Slot index of the aggregate of group g at level l (groups of kScanFan^l
+// tiles).
 __device__ __forceinline__ int64_t scan_slot(int l, int64_t g) {
   int64_t base = 0, cap = kScanTiles;
   for (int k = 0; k < l; ++k) {
     base += cap;
-    cap = (cap + 63) / 64;
+    cap = (cap + kScanFan - 1) / kScanFan;
   }
   return base + g;
 }
@@ -189,6 +187,49 @@ __global__ __launch_bounds__(256) void scan_heads_kernel(const int64_t* __restri
   tile_first[t] = ((uint64_t)(e + 1u) << 32) | (uint64_t)(uint32_t)s;
 }
 
+// One lane's V elements of each of its U pieces of tile t0 .. t0 + TE:
+// 16-byte loads when the tile is whole and aligned, else guarded element
+// loads with the neutral element past the end.
+template <Store S, Op O, int U, bool NT>
+__device__ __forceinline__ void tile_load(const typename Stored<S>::T* __restrict__ x, int64_t n, int64_t t0,
+                                          int64_t TE, bool aligned, int wave, int lane, u32x4 (&v)[U]) {
+  using T = typename Stored<S>::T;
+  constexpr int V = 16 / (int)sizeof(T);
+  if (aligned && t0 + TE <= n) {
+    const u32x4* p = (const u32x4*)(x + t0) + (int64_t)wave * U * 64 + lane;
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load16<NT>(p + u * 64);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t base = t0 + ((int64_t)(wave * U + u) * 64 + lane) * V;
+      struct E { T e[V]; } e;
+#pragma unroll
+      for (int k = 0; k < V; ++k) e.e[k] = (base + k < n) ? x[base + k] : stored_identity<S, O>();
+      v[u] = __builtin_bit_cast(u32x4, e);
+    }
+  }
+}
+
+// Segmented form: set the bit of every run start of tile t in `bits`
+// (cleared beforehand).  Starts come from the tagged first-head index of
+// the tile and the offsets that follow it.
+__device__ __forceinline__ void mark_heads(const ScanArgs& a, int64_t t, int64_t t0, int64_t TE, uint32_t tag,
+                                           uint32_t* bits) {
+  const uint64_t fw = a.tile_first[t];
+  if ((uint32_t)(fw >> 32) != tag) return;
+  const int64_t tend = (t0 + TE < a.n) ? t0 + TE : a.n;
+  for (int64_t s = (int64_t)(uint32_t)fw + threadIdx.x; s < a.nheads; s += blockDim.x) {
+    const int64_t p = a.heads[s];
+    if (p >= tend) break;
+    if (p >= t0) atomicOr(&bits[(p - t0) >> 5], 1u << ((p - t0) & 31));
+  }
+}
+
+__device__ __forceinline__ unsigned grab_tile(unsigned* ctl) {
+  return __hip_atomic_fetch_add(ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <Store S, Op O, bool SEG, int U, bool NT>
 __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   using R = Red<S, O>;
@@ -204,18 +245,21 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   using ItC = typename IC::I;
   constexpr int V = 16 / (int)sizeof(T);
   constexpr int OB = V * (int)sizeof(Out);  // output bytes per lane and piece: 16 or 32
+  constexpr int P = (int)(sizeof(Ch) / 4);  // words per published slot
+  constexpr int HW = SEG ? 1024 * U * V / 32 : 1;
   static_assert(OB % 16 == 0, "whole 16-byte stores");
 
   __shared__ ItA lds_wave[16];
   __shared__ ItC lds_pre;
-  __shared__ int64_t lds_tile;
-  __shared__ uint32_t lds_heads[SEG ? 1024 * U * V / 32 : 1];
+  __shared__ int64_t lds_next[2];
+  __shared__ uint32_t lds_heads[SEG ? 2 : 1][HW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int B = blockDim.x, W = B >> 6;
   const int64_t TE = (int64_t)B * U * V;
   const uint32_t tag = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
   const bool ex = a.exclusive != 0;
+  const bool aligned = a.aligned != 0;
   const T* __restrict__ x = (const T*)a.x;
   Out* __restrict__ out = (Out*)a.out;
   const auto combA = [](ItA p, ItA q) { return IA::comb(p, q); };
@@ -223,59 +267,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   const auto to_ch = [](ItA i) { return IC::with((Ch)IA::val(i), IA::flag(i)); };
   const auto to_acc = [](ItC i) { return IA::with((A)IC::val(i), IC::flag(i)); };
 
-  for (;;) {
-    if (tid == 0)
-      lds_tile = (int64_t)__hip_atomic_fetch_add(a.ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int64_t t = lds_tile;
-    if (t >= a.ntiles) break;
-    const int64_t t0 = t * TE;
-    const bool full = a.aligned && (t0 + TE <= a.n);
-
-    // Loads: lane's V elements of each piece (guarded element loads for the
-    // last tile or unaligned arrays; past-the-end lanes get the identity).
-    u32x4 v[U];
-    if (full) {
-      const u32x4* p = (const u32x4*)(x + t0) + (int64_t)wave * U * 64 + lane;
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = load16<NT>(p + u * 64);
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t base = t0 + ((int64_t)(wave * U + u) * 64 + lane) * V;
-        struct E { T e[V]; } e;
-#pragma unroll
-        for (int k = 0; k < V; ++k) e.e[k] = (base + k < a.n) ? x[base + k] : stored_identity<S, O>();
-        v[u] = __builtin_bit_cast(u32x4, e);
-      }
-    }
-
-    // Segmented: mark the run starts of this tile in an LDS bitmap.
-    uint32_t hb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) hb[u] = 0u;
-    if constexpr (SEG) {
-      for (int i = tid; i < (int)(TE / 32); i += B) lds_heads[i] = 0u;
-      __syncthreads();
-      const uint64_t fw = a.tile_first[t];
-      if ((uint32_t)(fw >> 32) == tag) {
-        const int64_t tend = (t0 + TE < a.n) ? t0 + TE : a.n;
-        for (int64_t s = (int64_t)(uint32_t)fw + tid; s < a.nheads; s += B) {
-          const int64_t p = a.heads[s];
-          if (p >= tend) break;
-          if (p >= t0) atomicOr(&lds_heads[(p - t0) >> 5], 1u << ((p - t0) & 31));
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int bit = ((wave * U + u) * 64 + lane) * V;
-        hb[u] = (lds_heads[bit >> 5] >> (bit & 31)) & ((1u << V) - 1u);
-      }
-    }
-
-    // Lane totals, then per piece a wavefront scan and the chain of pieces.
-    ItA excl[U];
+  // Lane totals of one tile, a wavefront scan per piece and the chain of
+  // pieces: excl[u] is the lane's exclusive prefix inside its wavefront's
+  // part of the tile, the return value the wavefront's aggregate.
+  const auto tile_scan = [&](const u32x4 (&v)[U], const uint32_t (&hb)[U], ItA (&excl)[U]) {
     ItA carry = IA::id();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -287,81 +282,165 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
       excl[u] = IA::comb(wave_shift_up(inc, IA::id()), carry);
       carry = IA::comb(readlane(inc, 63), carry);
     }
-    if (lane == 0) lds_wave[wave] = carry;
-    __syncthreads();
-    ItA wp = IA::id();  // prefix of the earlier wavefronts of this tile
-    for (int w = 0; w < wave; ++w) wp = IA::comb(lds_wave[w], wp);
-
-    // Wavefront 0: publish the tile's aggregate, fold its exclusive prefix.
-    if (wave == 0) {
-      ItA agg = IA::id();
-      for (int w = 0; w < W; ++w) agg = IA::comb(lds_wave[w], agg);
-      const ItC aggc = to_ch(agg);
-      if (lane == 0) slot_put<Ch, ItC, IC>(a.slots + kScanSlotWords * scan_slot(0, t), aggc, tag);
-      ItC P = IC::id();
-      ItC cur = aggc;  // aggregate of this tile's group at the current level
-      bool last = true;
-      int64_t g = t;
-      for (int l = 0; l < kScanLevels; ++l) {
-        const int pos = (int)(g & 63);
-        const int64_t parent = g >> 6;
-        ItC mine = IC::id();
-        if (lane < pos)
-          mine = slot_wait<Ch, ItC, IC>(a.slots + kScanSlotWords * scan_slot(l, parent * 64 + lane), tag,
-                                        a.ctl + 3);
-        const ItC F = readlane(wave_scan_incl(mine, IC::id(), combC), 63);
-        P = IC::comb(P, F);
-        if (last && pos == 63 && l + 1 < kScanLevels) {
-          cur = IC::comb(cur, F);
-          if (lane == 0) slot_put<Ch, ItC, IC>(a.slots + kScanSlotWords * scan_slot(l + 1, parent), cur, tag);
-        } else {
-          last = false;
-        }
-        if (parent == 0) break;
-        g = parent;
-      }
-      if (lane == 0) lds_pre = P;
+    return carry;
+  };
+  const auto head_bits = [&](const uint32_t* bits, uint32_t (&hb)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int bit = ((wave * U + u) * 64 + lane) * V;
+      hb[u] = SEG ? (bits[bit >> 5] >> (bit & 31)) & ((1u << V) - 1u) : 0u;
     }
-    __syncthreads();
-    const ItC P = lds_pre;
+  };
 
-    // Outputs: a left fold from each lane's prefix (the exclusive form
+  // Wavefront 0's look-back state for the current tile.  Lane
+  // kScanFan * l + j reads the aggregate of sibling j at level l of the tree
+  // (all levels in one load, issued as soon as the tile's own aggregate is
+  // out); the waits come later, level by level.
+  const int my_l = lane >> kScanFanLog, my_j = lane & (kScanFan - 1);
+  uint64_t lw[P];
+  bool lact = false;
+  const uint64_t* lsrc = a.slots;
+  ItC aggc = IC::id();
+  const auto publish_and_ask = [&](int64_t tt) {
+    ItA agg = IA::id();
+    for (int w = 0; w < W; ++w) agg = IA::comb(lds_wave[w], agg);
+    aggc = to_ch(agg);
+    if (lane == 0) slot_put<Ch, ItC, IC>(a.slots + kScanSlotWords * scan_slot(0, tt), aggc, tag);
+    const int64_t my_g = my_l < kScanLevels ? (tt >> (kScanFanLog * my_l)) : 0;
+    lact = my_l < kScanLevels && (my_l == 0 || my_g != 0) && my_j < (int)(my_g & (kScanFan - 1));
+    lsrc = a.slots + kScanSlotWords * scan_slot(my_l < kScanLevels ? my_l : 0, (my_g >> kScanFanLog) * kScanFan + my_j);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      lw[i] = lact ? __hip_atomic_load(lsrc + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+  };
+  // Fold the tile's exclusive prefix; a tile that completes a group
+  // publishes the group's aggregate as soon as that level is in, so group
+  // aggregates never wait for anything above them.
+  const auto finish_lookback = [&](int64_t tt) {
+    ItC Pre = IC::id();
+    ItC cur = aggc;
+    bool last = true;
+    int64_t g = tt;
+    for (int l = 0; l < kScanLevels; ++l) {
+      if (l > 0 && g == 0) break;  // no earlier groups at this level or above
+      scan_wait<P>(lw, lsrc, lact && my_l == l, tag, a.ctl + 3);
+      struct Wd { uint32_t q[P]; } wd;
+#pragma unroll
+      for (int i = 0; i < P; ++i) wd.q[i] = (uint32_t)lw[i];
+      const ItC got = (lact && my_l == l) ? IC::with(__builtin_bit_cast(Ch, wd), (uint32_t)(lw[0] >> 32) & 1u)
+                                          : IC::id();
+      const ItC F = readlane(wave_scan_incl(got, IC::id(), combC), 63);
+      Pre = IC::comb(Pre, F);
+      last = last && (g & (kScanFan - 1)) == kScanFan - 1;
+      if (last && l + 1 < kScanLevels) {
+        cur = IC::comb(cur, F);
+        if (lane == 0)
+          slot_put<Ch, ItC, IC>(a.slots + kScanSlotWords * scan_slot(l + 1, g >> kScanFanLog), cur, tag);
+      }
+      g >>= kScanFanLog;
+    }
+    return Pre;
+  };
+
+  // Pipeline.  Rule: between taking a tile and publishing its aggregate a
+  // work-group never waits for another tile (otherwise the aggregates of
+  // later tiles would wait on earlier look-backs: a chain along the array).
+  // So a tile is taken only after the previous tile's prefix is known, and
+  // its loads overlap the previous tile's stores.
+  if (tid == 0) lds_next[0] = grab_tile(a.ctl);
+  if constexpr (SEG)
+    for (int i = tid; i < (int)(TE / 32); i += B) lds_heads[0][i] = 0u;
+  __syncthreads();
+  int64_t t = lds_next[0];
+  u32x4 v[U];
+  uint32_t hb[U];
+  ItA excl[U];
+  ItA wp = IA::id();
+  if (t < a.ntiles) {
+    tile_load<S, O, U, NT>(x, a.n, t * TE, TE, aligned, wave, lane, v);
+    if constexpr (SEG) {
+      mark_heads(a, t, t * TE, TE, tag, lds_heads[0]);
+      __syncthreads();
+    }
+    head_bits(lds_heads[0], hb);
+    const ItA wagg = tile_scan(v, hb, excl);
+    if (lane == 0) lds_wave[wave] = wagg;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) wp = IA::comb(lds_wave[w], wp);
+    if (wave == 0) publish_and_ask(t);
+  }
+  int it = 0;
+  while (t < a.ntiles) {
+    const int nx = (it + 1) & 1;
+    const int64_t t0 = t * TE;
+    if (wave == 0) {
+      const ItC Pre = finish_lookback(t);
+      if (lane == 0) {
+        lds_pre = Pre;
+        lds_next[nx] = grab_tile(a.ctl);
+      }
+    }
+    if constexpr (SEG)
+      for (int i = tid; i < (int)(TE / 32); i += B) lds_heads[nx][i] = 0u;
+    __syncthreads();
+    const ItC Pt = lds_pre;
+    const int64_t tn = lds_next[nx];
+    u32x4 vn[U];
+    if (tn < a.ntiles) {
+      tile_load<S, O, U, NT>(x, a.n, tn * TE, TE, aligned, wave, lane, vn);
+      if constexpr (SEG) mark_heads(a, tn, tn * TE, TE, tag, lds_heads[nx]);
+    }
+
+    // Outputs of t: a left fold from each lane's prefix (the exclusive form
     // reports the value before each element, the neutral element at a run's
     // start).
     struct OE { Out e[V]; };
-    OE o[U];
+    const bool whole = aligned && t0 + TE <= a.n;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ItA run = to_acc(IC::comb(to_ch(IA::comb(excl[u], wp)), P));
+      ItA run = to_acc(IC::comb(to_ch(IA::comb(excl[u], wp)), Pt));
+      OE o;
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const bool h = ((hb[u] >> k) & 1u) != 0;
         const A before = h ? R::identity() : IA::val(run);
         run = IA::comb(IA::make(R::convert(lane_elem<T>(v[u], k)), h), run);
-        o[u].e[k] = R::finalize(ex ? before : IA::val(run));
+        o.e[k] = R::finalize(ex ? before : IA::val(run));
       }
-    }
-    if (full) {
-      struct OV { u32x4 q[OB / 16]; };
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const OV ov = __builtin_bit_cast(OV, o[u]);
-        u32x4* dst = (u32x4*)(out + t0) + ((int64_t)(wave * U + u) * 64 + lane) * (OB / 16);
+      const int64_t base = t0 + ((int64_t)(wave * U + u) * 64 + lane) * V;
+      if (whole) {
+        struct OV { u32x4 q[OB / 16]; };
+        const OV ov = __builtin_bit_cast(OV, o);
+        u32x4* dst = (u32x4*)(out + base);
 #pragma unroll
         for (int i = 0; i < OB / 16; ++i) {
           if constexpr (NT) __builtin_nontemporal_store(ov.q[i], dst + i);
           else dst[i] = ov.q[i];
         }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t base = t0 + ((int64_t)(wave * U + u) * 64 + lane) * V;
+      } else {
 #pragma unroll
         for (int k = 0; k < V; ++k)
-          if (base + k < a.n) out[base + k] = o[u].e[k];
+          if (base + k < a.n) out[base + k] = o.e[k];
       }
     }
+
+    // The next tile: its scan and aggregate, published at once.
+    if constexpr (SEG) __syncthreads();  // its run starts are marked
+    if (tn < a.ntiles) {
+      head_bits(lds_heads[SEG ? nx : 0], hb);
+      const ItA wagg = tile_scan(vn, hb, excl);
+      if (lane == 0) lds_wave[wave] = wagg;
+    }
+    __syncthreads();
+    if (tn < a.ntiles) {
+      wp = IA::id();
+      for (int w = 0; w < wave; ++w) wp = IA::comb(lds_wave[w], wp);
+      if (wave == 0) publish_and_ask(tn);
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = vn[u];
+    }
+    t = tn;
+    ++it;
   }
 
   // The last work-group out re-arms the counters and advances the epoch.

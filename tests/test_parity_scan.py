@@ -104,7 +104,8 @@ def test_scan_small_and_tile_edges(n, dtype, op):
 @pytest.mark.parametrize("block", [64, 256, 1024])
 def test_scan_tree_levels(block):
     # 64-wide work-groups make 1,024-element float32 tiles: 4,200,000 elements
-    # are 4,102 tiles, past the second level of the tree (4,096 tiles)
+    # are 4,102 tiles, so the tree of 8-wide groups has five levels (8^4 =
+    # 4,096 tiles) and the top level is partly filled
     rd.config_force("scan", {"block": block, "unroll": 4, "blocks_per_cu": 4, "nontemporal": 1, "layout": 0})
     try:
         x = data(4_200_000, "int32", "sum")
