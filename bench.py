@@ -341,6 +341,8 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of the 1 GiB input (counter calibration)")
+    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan"], default=None,
+                    help="run one secondary workload alone (for profiling) and print its results")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM-traffic summary of two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -367,6 +369,27 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     n = 2 ** 28
+    if args.only:
+        import oracle  # the sections check sampled results against the CPU oracle
+
+        xp = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
+        outp = torch.empty((), dtype=torch.float32, device=dev)
+        plain_spb = time_launches(lambda: rd.reduce(xp, "sum", out=outp), 20, 3, torch) / (4 * n)
+        del xp
+        torch.cuda.empty_cache()
+        if args.only == "scan":
+            res = bench_scan(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb)
+        elif args.only == "segmented":
+            res = bench_segmented(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb)
+        elif args.only == "rowwise":
+            res = bench_rowwise(rd, torch, args.steps, args.warmup, plain_spb)
+        else:
+            x = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
+            outc = torch.empty((), dtype=torch.float64, device=dev)
+            tc = time_launches(lambda: rd.reduce_compensated(x, out=outc), args.steps, args.warmup, torch)
+            res = {"ms": round(tc * 1e3, 4), "GBps": round(gbps(4 * n, tc), 1)}
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return 0
     log("generating input")
     x_np = W.plain(n, "float32", "sum", config=1, salt=28)
     x = torch.from_numpy(x_np).to(dev)
