@@ -18,7 +18,7 @@
 // the one that completes the count folds the partials in wavefront order and
 // writes the result.  The fold order does not depend on arrival order, so the
 // result is deterministic.  Empty segments are written with the neutral
-// element by a grid-stride pre-pass.
+// element by a grid-stride pass at the end.
 #pragma once
 
 #include "rd_device.hpp"
@@ -68,12 +68,14 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
   constexpr int K = U * V;  // elements per lane per window
   const int lane = threadIdx.x & 63;
 
-  // ---- pre-pass: empty segments get the neutral element
-  {
+  // Empty segments get the neutral element (no other path writes them:
+  // the walk over segments skips them).  Done last, so its loads do not
+  // delay the first data loads.
+  const auto fill_empty = [&]() {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += stride)
       if (offsets[s + 1] <= offsets[s]) out[s] = R::finalize(R::identity());
-  }
+  };
 
   // ---- this wavefront's piece
   Partition P;
@@ -81,7 +83,10 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   P.lo = offsets[0];
   P.hi = offsets[nseg];
-  if (P.hi <= P.lo) return;
+  if (P.hi <= P.lo) {
+    fill_empty();
+    return;
+  }
   P.V = V;
   {
     const uintptr_t a = (uintptr_t)(x + P.lo);
@@ -95,7 +100,33 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
     P.wt = P.nvec > 0 ? (P.nvec - 1) / P.per : 0;
   }
   const int64_t r0 = P.r0(w), r1 = P.r1(w);
-  if (r0 >= r1) return;
+  if (r0 >= r1) {
+    fill_empty();
+    return;
+  }
+
+  // The first window's loads go out before the segment search, so the
+  // search's dependent offset loads overlap them.
+  const int64_t v0 = min(w * P.per, P.nvec), v1 = min((w + 1) * P.per, P.nvec);
+  const u32x4* xv = (const u32x4*)(x + P.A);
+  // Windows of 64 x U vectors, software-pipelined: the next window's loads
+  // are issued before the current one is folded, so segment bookkeeping at
+  // boundaries overlaps memory latency.  Vectors at or past v1 are not read.
+  auto load_window = [&](int64_t vb, u32x4 (&raw)[U]) {
+    const int64_t nv = min((int64_t)(64 * U), v1 - vb);
+    if (nv == 64 * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        raw[u] = u32x4{0u, 0u, 0u, 0u};
+        if (u * 64 + lane < nv) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
+      }
+    }
+  };
+  u32x4 cur[U], nxt[U];
+  if (v0 < v1) load_window(v0, cur);
 
   // ---- segment containing r0: largest s < nseg with offsets[s] <= r0 (64-ary search)
   int64_t s;
@@ -233,27 +264,7 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
 
   if (w == 0 && P.A > P.lo) consume_scalar(P.lo, P.A);
 
-  const int64_t v0 = min(w * P.per, P.nvec), v1 = min((w + 1) * P.per, P.nvec);
-  const u32x4* xv = (const u32x4*)(x + P.A);
   auto rel_vec = [&](int k) { return (int32_t)(((k / V) * 64 + lane) * V + (k % V)); };
-  // Windows of 64 x U vectors, software-pipelined: the next window's loads
-  // are issued before the current one is folded, so segment bookkeeping at
-  // boundaries overlaps memory latency.  Vectors at or past v1 are not read.
-  auto load_window = [&](int64_t vb, u32x4 (&raw)[U]) {
-    const int64_t nv = min((int64_t)(64 * U), v1 - vb);
-    if (nv == 64 * U) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
-    } else {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        raw[u] = u32x4{0u, 0u, 0u, 0u};
-        if (u * 64 + lane < nv) raw[u] = load16<NT>(xv + vb + u * 64 + lane);
-      }
-    }
-  };
-  u32x4 cur[U], nxt[U];
-  if (v0 < v1) load_window(v0, cur);
   for (int64_t vb = v0; vb < v1; vb += 64 * U) {
     const int64_t vn = vb + 64 * U;
     if (vn < v1) load_window(vn, nxt);
@@ -286,6 +297,7 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
 
   // The last segment this wavefront touched.
   emit(s, fold_acc(), seg_begin, seg_end);
+  fill_empty();
 }
 
 template <class R, int U, bool NT>
