@@ -191,11 +191,11 @@ std::vector<TuneEntry> builtin_table() {
       t.push_back({RD_KIND_SEGMENTED, es, oc, 0, 62, {1024, 2, 1, 1, 0}});
     }
   // Row-wise (float32), measured at 4096 x 262144: the forward streams best
-  // with non-temporal loads; the write-only backward with plain stores.
+  // with non-temporal loads, the write-only backward with non-temporal stores.
   t.push_back({RD_KIND_ROWWISE, 4, 0, 0, 62, {256, 2, 4, 1, 0}});
   t.push_back({RD_KIND_ROWWISE, 4, 1, 0, 62, {256, 1, 8, 1, 0}});
-  t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 0, 0}});
-  t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 0, 0}});
+  t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 1, 0}});
+  t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 1, 0}});
   // Scans, measured for float32 sums at n = 2^28: large tiles (one
   // 1024-wide work-group per CU) keep the per-tile look-back cost small.
   for (int es : {2, 4, 8})
