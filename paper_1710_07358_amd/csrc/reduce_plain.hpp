@@ -118,8 +118,11 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
 // c collects those errors.  Pairs leave the work-item as double-double and
 // are merged in float64 (DPP, LDS and the last-block-done fold).
 static_assert(sizeof(dd) / 4 <= kPartialWords, "partial slot too small");
-template <Store S, int U, bool NT>
-__global__ __launch_bounds__(1024) void reduce_compensated_kernel(
+// LB: the largest work-group the instantiation serves.  (s, c) pairs double
+// the accumulator registers; with LB = 256 the compiler may give a wavefront
+// up to 512 VGPRs, so U = 8 and 16 run without spilling.
+template <Store S, int U, bool NT, int LB>
+__global__ __launch_bounds__(LB) void reduce_compensated_kernel(
     const typename Stored<S>::T* __restrict__ x, int64_t n, uint64_t* __restrict__ partial,
     unsigned* __restrict__ ticket, double* __restrict__ out, int layout) {
 #pragma clang fp contract(off)
@@ -206,9 +209,12 @@ hipError_t launch_plain(const void* x, int64_t n, void* out, const Scratch& ws, 
 template <Store S, int U, bool NT>
 hipError_t launch_comp(const void* x, int64_t n, void* out, const Scratch& ws, const Launch& l,
                        hipStream_t s) {
-  hipLaunchKernelGGL((reduce_compensated_kernel<S, U, NT>), dim3(l.grid), dim3(l.block), 0, s,
-                     (const typename Stored<S>::T*)x, n, ws.partial, ws.ticket, (double*)out,
-                     l.layout);
+  if (l.block <= 256)
+    hipLaunchKernelGGL((reduce_compensated_kernel<S, U, NT, 256>), dim3(l.grid), dim3(l.block), 0, s,
+                       (const typename Stored<S>::T*)x, n, ws.partial, ws.ticket, (double*)out, l.layout);
+  else
+    hipLaunchKernelGGL((reduce_compensated_kernel<S, U, NT, 1024>), dim3(l.grid), dim3(l.block), 0, s,
+                       (const typename Stored<S>::T*)x, n, ws.partial, ws.ticket, (double*)out, l.layout);
   return hipGetLastError();
 }
 
