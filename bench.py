@@ -426,6 +426,8 @@ def main() -> int:
     secondary = {}
     if not args.no_secondary:
         plain_spb = t / nbytes
+        tsum = time_launches(lambda: torch.sum(x), args.steps, args.warmup, torch)
+        secondary["torch_sum"] = {"ms": round(tsum * 1e3, 4), "GBps": round(gbps(nbytes, tsum), 1)}
         log("compensated sum")
         outc = torch.empty((), dtype=torch.float64, device=dev)
         tc = time_launches(lambda: rd.reduce_compensated(x, out=outc), args.steps, args.warmup, torch)
