@@ -262,7 +262,8 @@ rd_status rd_config_force(rd_kind kind, const rd_config* cfg);
 /* Load a tuned table written by the autotuner (NULL restores the built-in
  * defaults).  Format: one line per entry,
  *   kind dtype_size op_class log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout
- * with op_class 0 = sum/prod, 1 = min/max, 2 = and/or/xor; '#' starts a comment. */
+ * with op_class 0 = sum/prod, 1 = min/max, 2 = and/or/xor (for the row-wise kinds,
+ * which have no bitwise ops: 0 = sum, 2 = product); '#' starts a comment. */
 rd_status rd_tune_load(const char* path);
 
 /* Description of the last non-OK status returned on this thread. */

@@ -175,6 +175,13 @@ int op_class(rd_op op) {
   return 2;
 }
 
+// Row-wise kinds have no bitwise ops; their class 2 is the product, whose
+// forward and backward do different work from the sum's.
+int op_class(rd_kind kind, rd_op op) {
+  if ((kind == RD_KIND_ROWWISE || kind == RD_KIND_ROWWISE_BWD) && op == RD_PROD) return 2;
+  return op_class(op);
+}
+
 std::vector<TuneEntry> builtin_table() {
   // Defaults before tuning (measured on MI355X for float32 sums): few
   // resident wavefronts per CU stream best; non-temporal loads and XCD-grouped
@@ -194,8 +201,10 @@ std::vector<TuneEntry> builtin_table() {
   // with non-temporal loads, the write-only backward with non-temporal stores.
   t.push_back({RD_KIND_ROWWISE, 4, 0, 0, 62, {256, 2, 4, 1, 0}});
   t.push_back({RD_KIND_ROWWISE, 4, 1, 0, 62, {256, 1, 8, 1, 0}});
+  t.push_back({RD_KIND_ROWWISE, 4, 2, 0, 62, {256, 2, 4, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 1, 0}});
+  t.push_back({RD_KIND_ROWWISE_BWD, 4, 2, 0, 62, {256, 4, 1, 1, 0}});
   // Scans, measured for float32 sums at n = 2^28: large tiles (one
   // 1024-wide work-group per CU) keep the per-tile look-back cost small.
   for (int es : {2, 4, 8})
@@ -217,7 +226,7 @@ int log2_ceil(int64_t n) {
 rd_config choose_config(rd_kind kind, rd_dtype dt, rd_op op, int64_t n) {
   std::lock_guard<std::mutex> lock(g_mu);
   if (g_forced[kind]) return g_force_cfg[kind];
-  const int es = (int)rd_dtype_size(dt), oc = op_class(op), l = log2_ceil(n);
+  const int es = (int)rd_dtype_size(dt), oc = op_class(kind, op), l = log2_ceil(n);
   for (const TuneEntry& e : g_table)
     if (e.kind == (int)kind && e.esize == es && e.opclass == oc && l >= e.lo && l <= e.hi) return e.cfg;
   return rd_config{256, 8, 2, 0, 0};

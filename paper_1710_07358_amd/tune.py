@@ -103,8 +103,12 @@ def _case_runner(kind: str, esize: int, opclass: int, n: int, dev):
         return (lambda: rd.segmented(x, offs, op, out=out)), total * esize
     if kind in ("rowwise", "rowwise_bwd"):
         rows, cols = 4096, 262144
-        rop = {0: "sum", 1: "max"}[opclass]
-        x = torch.randn(rows, cols, device=dev)
+        rop = {0: "sum", 1: "max", 2: "prod"}[opclass]
+        if rop == "prod":  # the benchmark's product rows: factors near 1, zeros at rate 1e-4
+            x = torch.rand(rows, cols, device=dev) * 0.02 + 0.99
+            x[torch.rand(rows, cols, device=dev) < 1e-4] = 0.0
+        else:
+            x = torch.randn(rows, cols, device=dev)
         if kind == "rowwise":
             return (lambda: rd.rowreduce_forward(x, rop)), rows * cols * 4
         g = torch.randn(rows, device=dev)
@@ -144,15 +148,15 @@ def tune_table(kinds, esizes, log) -> list[str]:
             for opclass in (0, 1, 2):
                 if kind == "compensated" and opclass != 0:
                     continue
-                if row_kind and opclass == 2:
-                    continue
+
                 if esize == 2 and opclass == 2:
                     continue  # 16-bit bitwise: keep defaults
                 # the segmented, row-wise and scan launches are planned for one size bucket
                 buckets = [(0, 62, 1 << 28)] if kind in ("segmented", "rowwise", "rowwise_bwd", "scan") else BUCKETS
                 for lo, hi, n in buckets:
                     run, nbytes = _case_runner(kind, esize, opclass, n, dev)
-                    start = rd.config_get(kind, DTYPE_OF_SIZE[esize], OPS_OF_CLASS[opclass], n)
+                    cls_op = "prod" if (row_kind and opclass == 2) else OPS_OF_CLASS[opclass]
+                    start = rd.config_get(kind, DTYPE_OF_SIZE[esize], cls_op, n)
                     start["block"] = 256 if row_kind else start["block"]
                     best, t = descend(kind, start, run)
                     log(f"{kind} esize={esize} opclass={opclass} n=2^{n.bit_length() - 1}: {best} "
