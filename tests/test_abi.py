@@ -178,3 +178,11 @@ def test_bench_bandwidth_convention_matches_paper_table():
         assert abs(bench.gbps(n * esize, float(ms) / 1e3) - float(bw)) <= 1e-6 * float(bw), f
         base_ms = float(rows[2][1])
         assert abs(base_ms / float(ms) - float(speedup)) <= 1e-6 * float(speedup)
+
+
+def test_missing_library_fails_loudly(N, monkeypatch, tmp_path):
+    # No CPU fallback anywhere: without librd.so every entry point raises.
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "librd.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        N.lib()
