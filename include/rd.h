@@ -90,13 +90,14 @@ typedef struct rd_config {
  * fixed at 256, `unroll` is the number of 4-column stripes each work-item
  * handles per step (1, 2, 4 or 8; 16 is treated as 8), `blocks_per_cu` sizes
  * the persistent grid over rows, and `nontemporal` applies to the forward's
- * loads and the backward's stores.  For scans (RD_KIND_SCAN) `block` and
- * `blocks_per_cu` size the tiles (block x 4 x 16 bytes) and the persistent
- * grid, `nontemporal` applies to loads and stores, and `unroll` and `layout`
- * are ignored. */
+ * loads and the backward's stores.  For scans (RD_KIND_SCAN, and
+ * RD_KIND_SEGMENTED_SCAN for rd_segmented_scan) a tile is
+ * block x unroll x 16 bytes of input, with unroll 4 or 8 (8 when 8 or more
+ * is given, else 4); `blocks_per_cu` sizes the persistent grid,
+ * `nontemporal` applies to loads and stores, and `layout` is ignored. */
 typedef enum rd_kind {
     RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2, RD_KIND_ROWWISE = 3,
-    RD_KIND_ROWWISE_BWD = 4, RD_KIND_SCAN = 5
+    RD_KIND_ROWWISE_BWD = 4, RD_KIND_SCAN = 5, RD_KIND_SEGMENTED_SCAN = 6
 } rd_kind;
 
 /* ---- library and workspace management ---------------------------------- */
@@ -195,8 +196,9 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
  *   out : device array of n elements of rd_out_dtype(dt, op); it may be x
  *         itself when the output dtype has x's element size, and must not
  *         otherwise overlap x
- *   n   : 0 <= n <= 2^19 tiles of block x 4 x 16 bytes (2^31 float32 elements
- *         with 256-wide work-groups); more gives RD_ERR_INVALID_ARG
+ *   n   : 0 <= n <= 2^19 tiles of block x unroll x 16 bytes of input (2^33
+ *         float32 elements with the default 1024-wide work-groups); more gives
+ *         RD_ERR_INVALID_ARG
  * One pass and one launch: x is read once and out written once.  Each tile
  * publishes its aggregate and folds its prefix from earlier aggregates in a
  * fixed tree (groups of 8 tiles, groups of 8 groups, ...), so float results

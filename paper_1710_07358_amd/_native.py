@@ -19,7 +19,8 @@ RD_I32, RD_U32, RD_F32, RD_F64, RD_F16, RD_BF16, RD_I64, RD_U64 = range(8)
 RD_SUM, RD_PROD, RD_MIN, RD_MAX, RD_AND, RD_OR, RD_XOR = range(7)
 RD_OK, RD_ERR_INVALID_ARG, RD_ERR_UNSUPPORTED, RD_ERR_HIP, RD_ERR_NOMEM, RD_ERR_CAPTURE, RD_ERR_WORKSPACE = (
     0, -1, -2, -3, -4, -5, -6)
-RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD, RD_KIND_SCAN = range(6)
+(RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD, RD_KIND_SCAN,
+ RD_KIND_SEGMENTED_SCAN) = range(7)
 
 STATUS_NAMES = {0: "RD_OK", -1: "RD_ERR_INVALID_ARG", -2: "RD_ERR_UNSUPPORTED", -3: "RD_ERR_HIP",
                 -4: "RD_ERR_NOMEM", -5: "RD_ERR_CAPTURE", -6: "RD_ERR_WORKSPACE"}

@@ -21,7 +21,8 @@ OPS = {"sum": N.RD_SUM, "prod": N.RD_PROD, "min": N.RD_MIN, "max": N.RD_MAX,
        "and": N.RD_AND, "or": N.RD_OR, "xor": N.RD_XOR}
 KINDS = {"plain": N.RD_KIND_PLAIN, "compensated": N.RD_KIND_COMPENSATED,
          "segmented": N.RD_KIND_SEGMENTED, "rowwise": N.RD_KIND_ROWWISE,
-         "rowwise_bwd": N.RD_KIND_ROWWISE_BWD, "scan": N.RD_KIND_SCAN}
+         "rowwise_bwd": N.RD_KIND_ROWWISE_BWD, "scan": N.RD_KIND_SCAN,
+         "segmented_scan": N.RD_KIND_SEGMENTED_SCAN}
 
 
 def _dt(t: torch.Tensor) -> int:

@@ -205,16 +205,20 @@ std::vector<TuneEntry> builtin_table() {
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 0, 0, 62, {256, 4, 1, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 1, 0, 62, {256, 4, 1, 1, 0}});
   t.push_back({RD_KIND_ROWWISE_BWD, 4, 2, 0, 62, {256, 4, 1, 1, 0}});
-  // Scans, measured for float32 sums at n = 2^28: large tiles (one
-  // 1024-wide work-group per CU) keep the per-tile look-back cost small.
+  // Scans, measured at n = 2^28: large tiles (one 1024-wide work-group per
+  // CU, 8 loads per lane and piece) keep the per-tile look-back cost small;
+  // segmented scans of 16- and 64-bit data prefer 4 (fewer spilled registers).
   for (int es : {2, 4, 8})
-    for (int oc = 0; oc < 3; ++oc) t.push_back({RD_KIND_SCAN, es, oc, 0, 62, {1024, 4, 1, 1, 0}});
+    for (int oc = 0; oc < 3; ++oc) {
+      t.push_back({RD_KIND_SCAN, es, oc, 0, 62, {1024, 8, 1, 1, 0}});
+      t.push_back({RD_KIND_SEGMENTED_SCAN, es, oc, 0, 62, {1024, es == 4 ? 8 : 4, 1, 1, 0}});
+    }
   return t;
 }
 
 std::vector<TuneEntry> g_table = builtin_table();
-constexpr int kKinds = 6;
-bool g_forced[kKinds] = {false, false, false, false, false, false};
+constexpr int kKinds = 7;
+bool g_forced[kKinds] = {false, false, false, false, false, false, false};
 rd_config g_force_cfg[kKinds];
 
 int log2_ceil(int64_t n) {
@@ -305,17 +309,17 @@ SegFn segmented_launcher(rd_dtype dt, rd_op op, int unroll, bool nt) {
   return nullptr;
 }
 
-ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, bool nt) {
+ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, int u, bool nt) {
   const bool bitwise = (op == RD_AND || op == RD_OR || op == RD_XOR);
   switch (dt) {
     case RD_I32:
-    case RD_U32: return scan_int(dt, op, seg, nt);
-    case RD_F32: return bitwise ? scan_int(RD_U32, op, seg, nt) : scan_f32(op, seg, nt);
-    case RD_F64: return bitwise ? scan_int64(RD_U64, op, seg, nt) : scan_f64(op, seg, nt);
+    case RD_U32: return scan_int(dt, op, seg, u, nt);
+    case RD_F32: return bitwise ? scan_int(RD_U32, op, seg, u, nt) : scan_f32(op, seg, u, nt);
+    case RD_F64: return bitwise ? scan_int64(RD_U64, op, seg, u, nt) : scan_f64(op, seg, u, nt);
     case RD_F16:
-    case RD_BF16: return scan_half(dt, op, seg, nt);
+    case RD_BF16: return scan_half(dt, op, seg, u, nt);
     case RD_I64:
-    case RD_U64: return scan_int64(dt, op, seg, nt);
+    case RD_U64: return scan_int64(dt, op, seg, u, nt);
   }
   return nullptr;
 }
@@ -345,15 +349,16 @@ rd_status scan_call(const char* name, const void* x, int64_t n, const int64_t* h
   if ((st = current_device(&dev, &info)) != RD_OK) return st;
   rd_workspace* w;
   if ((st = resolve_workspace(ws, dev, (hipStream_t)stream, &w)) != RD_OK) return st;
-  const rd_config cfg = choose_config(RD_KIND_SCAN, dt, op, n);
-  const int64_t tile = (int64_t)cfg.block * rd::kScanUnroll * (int64_t)(16 / es);
+  const rd_config cfg = choose_config(seg ? RD_KIND_SEGMENTED_SCAN : RD_KIND_SCAN, dt, op, n);
+  const int unroll = cfg.unroll >= 8 ? 8 : 4;  // the instantiated tile depths
+  const int64_t tile = (int64_t)cfg.block * unroll * (int64_t)(16 / es);
   const int64_t ntiles = (n + tile - 1) / tile;
   if (ntiles > rd::kScanTiles)
     return fail(RD_ERR_INVALID_ARG, "%s: n = %lld needs %lld tiles of %lld elements; at most %lld per call", name,
                 (long long)n, (long long)ntiles, (long long)tile, (long long)rd::kScanTiles);
-  rd::ScanFn fn = rd::scan_launcher(dt, op, seg, cfg.nontemporal != 0);
+  rd::ScanFn fn = rd::scan_launcher(dt, op, seg, unroll, cfg.nontemporal != 0);
   if (!fn) return fail(RD_ERR_UNSUPPORTED, "%s: no kernel for dtype %d op %d", name, (int)dt, (int)op);
-  const rd::Launch l{cfg.block, std::max(1, cfg.blocks_per_cu * info.cus), rd::kScanUnroll, cfg.nontemporal != 0, 0};
+  const rd::Launch l{cfg.block, std::max(1, cfg.blocks_per_cu * info.cus), unroll, cfg.nontemporal != 0, 0};
   const rd::ScanCall c{x, n, out, exclusive != 0, seg ? heads : nullptr, seg ? nheads : 0};
   hipError_t e = fn(c, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, name);
@@ -589,14 +594,14 @@ rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int6
 }
 
 rd_status rd_config_get(rd_kind kind, rd_dtype dt, rd_op op, int64_t n, rd_config* cfg) {
-  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_SCAN || !valid_dtype(dt) || !valid_op(op))
+  if (!cfg || kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED_SCAN || !valid_dtype(dt) || !valid_op(op))
     return fail(RD_ERR_INVALID_ARG, "rd_config_get: bad argument");
   *cfg = choose_config(kind, dt, op, n);
   return RD_OK;
 }
 
 rd_status rd_config_force(rd_kind kind, const rd_config* cfg) {
-  if (kind < RD_KIND_PLAIN || kind > RD_KIND_SCAN) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
+  if (kind < RD_KIND_PLAIN || kind > RD_KIND_SEGMENTED_SCAN) return fail(RD_ERR_INVALID_ARG, "rd_config_force: bad kind");
   if (cfg && !valid_config(*cfg))
     return fail(RD_ERR_INVALID_ARG, "rd_config_force: block %d unroll %d blocks_per_cu %d nontemporal %d layout %d",
                 cfg->block, cfg->unroll, cfg->blocks_per_cu, cfg->nontemporal, cfg->layout);

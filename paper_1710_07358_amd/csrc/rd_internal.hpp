@@ -37,16 +37,16 @@ struct Scratch {
   uint64_t* scan_slots;       // kScanSlots x kScanSlotWords words
 };
 
-// Scan tiles per call (block x U x V elements each), fan-out and levels of
-// the tree of tile aggregates (kScanFan^kScanLevels >= kScanTiles), words
-// per published slot, epoch range, 16-byte loads per lane and piece.
+// Scan tiles per call (block x U x V elements each, U = 4 or 8 16-byte
+// loads per lane and piece), fan-out and levels of the tree of tile
+// aggregates (kScanFan^kScanLevels >= kScanTiles), words per published slot,
+// epoch range.
 constexpr int64_t kScanTiles = 1 << 19;
 constexpr int kScanFanLog = 3;
 constexpr int kScanFan = 1 << kScanFanLog;
 constexpr int kScanLevels = 7;
 constexpr int kScanSlotWords = 2;
 constexpr unsigned kScanEpochs = 0x7FFFFFFFu;
-constexpr int kScanUnroll = 4;
 // Slots: the group aggregates of every level.
 constexpr int64_t scan_slots_total() {
   int64_t total = 0, cap = kScanTiles;
@@ -86,13 +86,14 @@ struct ScanCall {
 };
 using ScanFn = hipError_t (*)(const ScanCall& c, const Scratch& ws, const Launch& l, hipStream_t s);
 
-// Scan kernels (plain when seg is false).  nullptr when (dt, op) is not offered.
-ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, bool nontemporal);
-ScanFn scan_int(rd_dtype dt, rd_op op, bool seg, bool nt);    // RD_I32 / RD_U32, 32-bit bitwise
-ScanFn scan_f32(rd_op op, bool seg, bool nt);
-ScanFn scan_f64(rd_op op, bool seg, bool nt);                 // also 64-bit bitwise of float64
-ScanFn scan_int64(rd_dtype dt, rd_op op, bool seg, bool nt);  // RD_I64 / RD_U64
-ScanFn scan_half(rd_dtype dt, rd_op op, bool seg, bool nt);   // RD_F16 / RD_BF16, 16-bit bitwise
+// Scan kernels (plain when seg is false), U = 4 or 8.  nullptr when (dt, op)
+// is not offered or U has no instantiation.
+ScanFn scan_launcher(rd_dtype dt, rd_op op, bool seg, int unroll, bool nontemporal);
+ScanFn scan_int(rd_dtype dt, rd_op op, bool seg, int u, bool nt);    // RD_I32 / RD_U32, 32-bit bitwise
+ScanFn scan_f32(rd_op op, bool seg, int u, bool nt);
+ScanFn scan_f64(rd_op op, bool seg, int u, bool nt);                 // also 64-bit bitwise of float64
+ScanFn scan_int64(rd_dtype dt, rd_op op, bool seg, int u, bool nt);  // RD_I64 / RD_U64
+ScanFn scan_half(rd_dtype dt, rd_op op, bool seg, int u, bool nt);   // RD_F16 / RD_BF16, 16-bit bitwise
 
 // Arg-reduction (min/max with the lowest index); unroll 2, 4 or 8.
 ArgFn arg_launcher(rd_dtype dt, bool is_max, int unroll, bool nontemporal);

@@ -485,8 +485,10 @@ hipError_t launch_scan(const ScanCall& c, const Scratch& ws, const Launch& l, hi
   return hipGetLastError();
 }
 
-template <Store S, Op O, bool SEG> ScanFn scan_pick(bool nt) {
-  return nt ? &launch_scan<S, O, SEG, kScanUnroll, true> : &launch_scan<S, O, SEG, kScanUnroll, false>;
+template <Store S, Op O, bool SEG> ScanFn scan_pick(int u, bool nt) {
+  if (u == 4) return nt ? &launch_scan<S, O, SEG, 4, true> : &launch_scan<S, O, SEG, 4, false>;
+  if (u == 8) return nt ? &launch_scan<S, O, SEG, 8, true> : &launch_scan<S, O, SEG, 8, false>;
+  return nullptr;
 }
 
 }  // namespace rd

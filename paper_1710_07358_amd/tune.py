@@ -19,6 +19,7 @@ import statistics
 import sys
 import time
 
+import numpy as np
 import torch
 
 from . import api as rd
@@ -38,11 +39,14 @@ SPACE = {
                 "nontemporal": [0, 1], "layout": [0]},
     "rowwise_bwd": {"block": [256], "unroll": [1, 2, 4, 8], "blocks_per_cu": [1, 2, 4, 8],
                     "nontemporal": [0, 1], "layout": [0]},
-    # scans: tile = block x 4 x 16 bytes; unroll and layout do not apply
-    "scan": {"block": [256, 512, 1024], "unroll": [4], "blocks_per_cu": [1, 2, 3, 4],
+    # scans: tile = block x unroll x 16 bytes; layout does not apply
+    "scan": {"block": [256, 512, 1024], "unroll": [4, 8], "blocks_per_cu": [1, 2, 3, 4],
              "nontemporal": [0, 1], "layout": [0]},
+    "segmented_scan": {"block": [256, 512, 1024], "unroll": [4, 8], "blocks_per_cu": [1, 2, 3, 4],
+                       "nontemporal": [0, 1], "layout": [0]},
 }
-KIND_ID = {"plain": 0, "compensated": 1, "segmented": 2, "rowwise": 3, "rowwise_bwd": 4, "scan": 5}
+KIND_ID = {"plain": 0, "compensated": 1, "segmented": 2, "rowwise": 3, "rowwise_bwd": 4, "scan": 5,
+           "segmented_scan": 6}
 
 
 def time_call(fn, reps: int = 20, batches: int = 3, warm_s: float = 0.05) -> float:
@@ -125,13 +129,18 @@ def _case_runner(kind: str, esize: int, opclass: int, n: int, dev):
         x = torch.rand(n, device=dev).to(dtype)
         out = torch.empty((), dtype=torch.float64, device=dev)
         return (lambda: rd.reduce_compensated(x, out=out)), n * esize
-    if kind == "scan":
+    if kind in ("scan", "segmented_scan"):
         if dtype.is_floating_point:
             x = torch.rand(n, device=dev).to(dtype)
         else:
             x = torch.randint(-1000, 1000, (n,), device=dev, dtype=dtype)
         out = torch.empty(n, dtype=rd.out_dtype(dtype, op), device=dev)
-        return (lambda: rd.scan(x, op, out=out)), n * (esize + out.element_size())
+        if kind == "scan":
+            return (lambda: rd.scan(x, op, out=out)), n * (esize + out.element_size())
+        from . import workloads as W
+        off = W.offsets_from_lengths(W.segment_lengths())
+        offs = torch.from_numpy(np.minimum(off, n)).to(dev)
+        return (lambda: rd.scan(x, op, out=out, offsets=offs)), n * (esize + out.element_size())
     raise ValueError(kind)
 
 
@@ -152,7 +161,8 @@ def tune_table(kinds, esizes, log) -> list[str]:
                 if esize == 2 and opclass == 2:
                     continue  # 16-bit bitwise: keep defaults
                 # the segmented, row-wise and scan launches are planned for one size bucket
-                buckets = [(0, 62, 1 << 28)] if kind in ("segmented", "rowwise", "rowwise_bwd", "scan") else BUCKETS
+                buckets = [(0, 62, 1 << 28)] if kind in ("segmented", "rowwise", "rowwise_bwd", "scan",
+                                                         "segmented_scan") else BUCKETS
                 for lo, hi, n in buckets:
                     run, nbytes = _case_runner(kind, esize, opclass, n, dev)
                     cls_op = "prod" if (row_kind and opclass == 2) else OPS_OF_CLASS[opclass]
@@ -192,7 +202,7 @@ def unroll_sweep(n: int, log) -> list[dict]:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None, help="write the tuned table here")
-    ap.add_argument("--kinds", default="plain,compensated,segmented,rowwise,rowwise_bwd,scan")
+    ap.add_argument("--kinds", default="plain,compensated,segmented,rowwise,rowwise_bwd,scan,segmented_scan")
     ap.add_argument("--esizes", default="2,4,8")
     ap.add_argument("--unroll-sweep", action="store_true")
     args = ap.parse_args()

@@ -142,7 +142,8 @@ def test_config_force_and_tune_table(N, tmp_path):
     assert lib.rd_config_force(N.RD_KIND_PLAIN, None) == N.RD_OK
     assert lib.rd_config_get(N.RD_KIND_SCAN, N.RD_F32, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
     assert got.block % 64 == 0 and got.blocks_per_cu >= 1
-    assert lib.rd_config_force(N.RD_KIND_SCAN + 1, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_config_get(N.RD_KIND_SEGMENTED_SCAN, N.RD_BF16, N.RD_SUM, 1 << 28, ctypes.byref(got)) == N.RD_OK
+    assert lib.rd_config_force(N.RD_KIND_SEGMENTED_SCAN + 1, None) == N.RD_ERR_INVALID_ARG
     table = tmp_path / "tune.txt"
     table.write_text("# kind esize opclass lo hi block unroll bpc nt layout\n0 4 0 20 30 1024 4 2 1 1\n")
     assert lib.rd_tune_load(str(table).encode()) == N.RD_OK

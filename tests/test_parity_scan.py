@@ -101,20 +101,26 @@ def test_scan_small_and_tile_edges(n, dtype, op):
     run_scan(x, op, dtype, True)
 
 
-@pytest.mark.parametrize("block", [64, 256, 1024])
-def test_scan_tree_levels(block):
-    # 64-wide work-groups make 1,024-element float32 tiles: 4,200,000 elements
-    # are 4,102 tiles, so the tree of 8-wide groups has five levels (8^4 =
-    # 4,096 tiles) and the top level is partly filled
-    rd.config_force("scan", {"block": block, "unroll": 4, "blocks_per_cu": 4, "nontemporal": 1, "layout": 0})
+@pytest.mark.parametrize("block,unroll", [(64, 4), (64, 8), (256, 4), (1024, 8)])
+def test_scan_tree_levels(block, unroll):
+    # 64-wide work-groups make float32 tiles of 64 x unroll x 4 elements:
+    # 8,400,000 elements are 8,203 (unroll 4) or 4,102 (unroll 8) tiles, so the
+    # tree of 8-wide groups has five levels (8^4 = 4,096 tiles) and its top
+    # level is partly filled
+    cfg = {"block": block, "unroll": unroll, "blocks_per_cu": 4, "nontemporal": 1, "layout": 0}
+    rd.config_force("scan", cfg)
+    rd.config_force("segmented_scan", cfg)
     try:
-        x = data(4_200_000, "int32", "sum")
+        x = data(8_400_000, "int32", "sum")
         run_scan(x, "sum", "int32", False)
         run_scan(x, "sum", "int32", True)
+        heads = np.arange(0, 8_400_000, 77_777, dtype=np.int64)
+        run_scan(x, "sum", "int32", False, heads=heads)
         f = data(300_007, "float32", "sum")
         run_scan(f, "sum", "float32", False)
     finally:
         rd.config_force("scan", None)
+        rd.config_force("segmented_scan", None)
 
 
 def test_scan_one_work_group_and_wide_grid():
