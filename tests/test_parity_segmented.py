@@ -117,6 +117,20 @@ def test_segmented_single_segment_equals_plain():
     assert seg.item() == plain.item() == oracle.reduce(x_np, "max", "float32")
 
 
+@pytest.mark.parametrize("block", [64, 1024])
+def test_segmented_one_segment_over_every_work_group(block):
+    # every wavefront's piece crosses its range: the pieces combine per
+    # work-group (1 or 16 wavefronts) and then across all work-groups
+    x_np = W.plain(2 ** 23 + 5, "int32", "sum", salt=11)
+    off = np.array([0, x_np.size], np.int64)
+    try:
+        rd.config_force("segmented", dict(block=block, unroll=2, blocks_per_cu=2, nontemporal=1, layout=0))
+        run(x_np, off, "sum", "int32")
+        run(x_np, np.array([0, 3, x_np.size - 2, x_np.size], np.int64), "xor", "int32")
+    finally:
+        rd.config_force("segmented", None)
+
+
 def test_segmented_long_segments_span_many_wavefronts():
     lens = np.array([1, 2 ** 22, 5, 2 ** 22 - 1, 3, 2 ** 21 + 17], np.int64)
     off = W.offsets_from_lengths(lens)
