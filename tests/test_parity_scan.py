@@ -1,11 +1,13 @@
 """Scan (inclusive / exclusive, plain and segmented): HIP path against the CPU oracle.
 
-Tolerances for float sums follow from the arithmetic of the kernel: an output
-is the exact prefix plus the rounding of at most V (lane) + 7 (DPP scan) + U
-(pieces) + 16 (wavefronts) + 3 (tile prefix, conversions) additions, each
+Tolerances for float sums follow from the arithmetic of the kernel: a term
+reaches an output through at most V - 1 (lane total) + 7 (DPP scan) + U - 1
+(pieces) + 1 + 15 (earlier wavefronts) + 1 + 1 (tile prefix, rounding to the
+accumulator) + V (the lane's running fold) = 2V + U + 24 roundings, each
 bounded by u times the running sum of |x| (u = 2^-24 for float32, float16 and
-bfloat16 data, which accumulate in float32; 2^-53 for float64), so
-|out - exact| <= 32 u sum|x| over the prefix.  Products accumulate in float64:
+bfloat16 data, which accumulate in float32; 2^-53 for float64).  With V <= 8
+and U <= 8 that is at most 48, so |out - exact| <= 48 u sum|x| over the prefix
+(tile prefixes travel in float64 and add far less).  Products accumulate in float64:
 any product tree of k factors is within (k-1) 2^-53 of the exact product,
 plus one float32 rounding of the output.
 """
@@ -56,8 +58,8 @@ def check_scan(x_np, op, dtype, out, exclusive, heads=None):
         u = 2.0 ** -53 if dtype == "float64" else 2.0 ** -24
         scale = oracle.scan(abs_storage(x_np, dtype), "sum", dtype, exclusive=exclusive, heads=heads)
         err = np.abs(got - ref)
-        bad = np.nonzero(err > 32 * u * scale)[0]
-        assert bad.size == 0, f"sum/{dtype}: {bad.size} beyond 32u sum|x|, first at {bad[:5]}: " \
+        bad = np.nonzero(err > 48 * u * scale)[0]
+        assert bad.size == 0, f"sum/{dtype}: {bad.size} beyond 48u sum|x|, first at {bad[:5]}: " \
                               f"got {got[bad[:5]]}, exact {ref[bad[:5]]}"
         return
     # products: k factors in the prefix (position inside the run)
@@ -243,4 +245,4 @@ def test_scan_full_size_int32_and_sampled_float32():
     for i in (4095, 4096 * 64 + 5, (1 << 27) + 12_345, n - 1):
         ref, asum = oracle.exact_sum(xf_np[: i + 1], "float32")
         got_i = float(out[i].item())
-        assert abs(got_i - ref) <= 32 * 2.0 ** -24 * asum, (i, got_i, ref)
+        assert abs(got_i - ref) <= 48 * 2.0 ** -24 * asum, (i, got_i, ref)
