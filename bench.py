@@ -260,6 +260,31 @@ def bench_scan(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
     return res
 
 
+def bench_paper_designs(rd, torch, steps, warmup):
+    """The paper's two designs (Section 2.3 two-stage; Section 3 unrolled F
+    times with the barrier-free tree) beside this library's kernel, float32
+    sum, at the paper's n = 5,533,214 and at 2^28."""
+    dev = torch.device("cuda")
+    res = {}
+    for n in (5_533_214, 2 ** 28):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(171007358 + 5000)
+        x = torch.rand(n, device=dev, generator=gen) * 2 - 1
+        out = torch.empty((), device=dev)
+        row = {}
+        t = time_launches(lambda: rd.reduce(x, "sum", out=out), steps, warmup, torch)
+        row["library"] = {"ms": round(t * 1e3, 5), "GBps": round(gbps(4 * n, t), 1)}
+        t = time_launches(lambda: rd.reduce_paper_design(x, 0, 1, out=out), steps, warmup, torch)
+        row["two_stage"] = {"ms": round(t * 1e3, 5), "GBps": round(gbps(4 * n, t), 1)}
+        for f in (1, 2, 4, 8, 16):
+            t = time_launches(lambda: rd.reduce_paper_design(x, 1, f, out=out), steps, warmup, torch)
+            row[f"unrolled_F{f}"] = {"ms": round(t * 1e3, 5), "GBps": round(gbps(4 * n, t), 1)}
+        res[str(n)] = row
+        del x
+        torch.cuda.empty_cache()
+    return res
+
+
 # ---------------------------------------------------------------- HBM traffic
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_reduce_kernel_f32_sum_2p28.txt")
@@ -341,7 +366,7 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of the 1 GiB input (counter calibration)")
-    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan"], default=None,
+    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs"], default=None,
                     help="run one secondary workload alone (for profiling) and print its results")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM-traffic summary of two rocprofv3 --pmc runs and exit")
@@ -383,6 +408,8 @@ def main() -> int:
             res = bench_segmented(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb)
         elif args.only == "rowwise":
             res = bench_rowwise(rd, torch, args.steps, args.warmup, plain_spb)
+        elif args.only == "paper_designs":
+            res = bench_paper_designs(rd, torch, args.steps, args.warmup)
         else:
             x = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
             outc = torch.empty((), dtype=torch.float64, device=dev)
@@ -445,6 +472,8 @@ def main() -> int:
         secondary["rowwise"] = bench_rowwise(rd, torch, max(args.steps // 5, 3), 2, plain_spb)
         log("scan")
         secondary["scan"] = bench_scan(rd, W, oracle, torch, np, max(args.steps // 5, 5), 2, plain_spb)
+        log("the paper's designs")
+        secondary["paper_designs"] = bench_paper_designs(rd, torch, max(args.steps // 5, 5), 2)
         if not args.no_precision:
             log("precision sets")
             secondary["precision"] = bench_precision(rd, W, oracle, torch, n)
