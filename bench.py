@@ -260,6 +260,29 @@ def bench_scan(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
     return res
 
 
+def bench_shard(rd, torch, steps, warmup):
+    """One GPU's share of the 8-way sharded headline: 2^25 float32 (128 MiB).
+    It fits the 256 MB MALL, so the cold figure rotates over 4 such buffers
+    (512 MiB); the hot figure re-reads one buffer."""
+    dev = torch.device("cuda")
+    n = 2 ** 25
+    bufs = [torch.rand(n, device=dev) for _ in range(4)]
+    out = torch.empty((), device=dev)
+    t_hot = time_launches(lambda: rd.reduce(bufs[0], "sum", out=out), steps, warmup, torch)
+    state = {"i": 0}
+
+    def rotate():
+        state["i"] = (state["i"] + 1) % 4
+        rd.reduce(bufs[state["i"]], "sum", out=out)
+
+    t_cold = time_launches(rotate, 4 * steps, warmup, torch)
+    res = {"n": n, "cold_ms": round(t_cold * 1e3, 5), "cold_GBps": round(gbps(4 * n, t_cold), 1),
+           "hot_ms": round(t_hot * 1e3, 5), "hot_GBps": round(gbps(4 * n, t_hot), 1)}
+    del bufs
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_paper_designs(rd, torch, steps, warmup):
     """The paper's two designs (Section 2.3 two-stage; Section 3 unrolled F
     times with the barrier-free tree) beside this library's kernel, float32
@@ -366,7 +389,8 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of the 1 GiB input (counter calibration)")
-    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs"], default=None,
+    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs", "shard"],
+                    default=None,
                     help="run one secondary workload alone (for profiling) and print its results")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM-traffic summary of two rocprofv3 --pmc runs and exit")
@@ -410,6 +434,8 @@ def main() -> int:
             res = bench_rowwise(rd, torch, args.steps, args.warmup, plain_spb)
         elif args.only == "paper_designs":
             res = bench_paper_designs(rd, torch, args.steps, args.warmup)
+        elif args.only == "shard":
+            res = bench_shard(rd, torch, args.steps, args.warmup)
         else:
             x = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
             outc = torch.empty((), dtype=torch.float64, device=dev)
@@ -472,6 +498,8 @@ def main() -> int:
         secondary["rowwise"] = bench_rowwise(rd, torch, max(args.steps // 5, 3), 2, plain_spb)
         log("scan")
         secondary["scan"] = bench_scan(rd, W, oracle, torch, np, max(args.steps // 5, 5), 2, plain_spb)
+        log("one GPU's shard")
+        secondary["shard_2p25"] = bench_shard(rd, torch, args.steps, args.warmup)
         log("the paper's designs")
         secondary["paper_designs"] = bench_paper_designs(rd, torch, max(args.steps // 5, 5), 2)
         if not args.no_precision:
