@@ -262,34 +262,60 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   const bool aligned = a.aligned != 0;
   const T* __restrict__ x = (const T*)a.x;
   Out* __restrict__ out = (Out*)a.out;
+  // Head bits of a lane: V bits per piece, piece u at bit u * V.
+  using HB = typename std::conditional<(U * V > 32), uint64_t, uint32_t>::type;
+  using IP = ScanItem<A, Combiner<O, A>, false>;  // items of a piece without run starts
   const auto combA = [](ItA p, ItA q) { return IA::comb(p, q); };
+  const auto combP = [](A p, A q) { return IP::comb(p, q); };
   const auto combC = [](ItC p, ItC q) { return IC::comb(p, q); };
   const auto to_ch = [](ItA i) { return IC::with((Ch)IA::val(i), IA::flag(i)); };
   const auto to_acc = [](ItC i) { return IA::with((A)IC::val(i), IC::flag(i)); };
+  const auto piece_bits = [](HB hb, int u) -> uint32_t {
+    return SEG ? (uint32_t)(hb >> (u * V)) & ((1u << V) - 1u) : 0u;
+  };
 
   // Lane totals of one tile, a wavefront scan per piece and the chain of
   // pieces: excl[u] is the lane's exclusive prefix inside its wavefront's
-  // part of the tile, the return value the wavefront's aggregate.
-  const auto tile_scan = [&](const u32x4 (&v)[U], const uint32_t (&hb)[U], ItA (&excl)[U]) {
+  // part of the tile, the return value the wavefront's aggregate.  A piece
+  // in which no lane holds a run start (bit u of `quiet`, the same in every
+  // lane) is scanned on bare values: with every flag clear the (value, flag)
+  // combine performs the same operations in the same order, so the result
+  // is identical, and runs are typically far longer than a piece.
+  const auto tile_scan = [&](const u32x4 (&v)[U], HB hb, ItA (&excl)[U], uint32_t& quiet) {
     ItA carry = IA::id();
+    quiet = 0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ItA r = IA::id();
+      const uint32_t pb = piece_bits(hb, u);
+      if (!SEG || __builtin_amdgcn_ballot_w64(pb != 0u) == 0ull) {
+        A r = IP::id();
 #pragma unroll
-      for (int k = 0; k < V; ++k)
-        r = IA::comb(IA::make(R::convert(lane_elem<T>(v[u], k)), (hb[u] >> k) & 1u), r);
-      const ItA inc = wave_scan_incl(r, IA::id(), combA);
-      excl[u] = IA::comb(wave_shift_up(inc, IA::id()), carry);
-      carry = IA::comb(readlane(inc, 63), carry);
+        for (int k = 0; k < V; ++k) r = IP::comb(R::convert(lane_elem<T>(v[u], k)), r);
+        const A inc = wave_scan_incl(r, IP::id(), combP);
+        excl[u] = IA::comb(IA::with(wave_shift_up(inc, IP::id()), 0u), carry);
+        carry = IA::comb(IA::with(readlane(inc, 63), 0u), carry);
+        quiet |= 1u << u;
+      } else {
+        ItA r = IA::id();
+#pragma unroll
+        for (int k = 0; k < V; ++k) r = IA::comb(IA::make(R::convert(lane_elem<T>(v[u], k)), (pb >> k) & 1u), r);
+        const ItA inc = wave_scan_incl(r, IA::id(), combA);
+        excl[u] = IA::comb(wave_shift_up(inc, IA::id()), carry);
+        carry = IA::comb(readlane(inc, 63), carry);
+      }
     }
     return carry;
   };
-  const auto head_bits = [&](const uint32_t* bits, uint32_t (&hb)[U]) {
+  const auto head_bits = [&](const uint32_t* bits) -> HB {
+    HB hb = 0;
+    if constexpr (SEG) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int bit = ((wave * U + u) * 64 + lane) * V;
-      hb[u] = SEG ? (bits[bit >> 5] >> (bit & 31)) & ((1u << V) - 1u) : 0u;
+      for (int u = 0; u < U; ++u) {
+        const int bit = ((wave * U + u) * 64 + lane) * V;
+        hb |= (HB)((bits[bit >> 5] >> (bit & 31)) & ((1u << V) - 1u)) << (u * V);
+      }
     }
+    return hb;
   };
 
   // Wavefront 0's look-back state for the current tile.  Lane
@@ -353,7 +379,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   __syncthreads();
   int64_t t = lds_next[0];
   u32x4 v[U];
-  uint32_t hb[U];
+  HB hb = 0;
+  uint32_t quiet = 0u;
   ItA excl[U];
   ItA wp = IA::id();
   if (t < a.ntiles) {
@@ -362,8 +389,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
       mark_heads(a, t, t * TE, TE, tag, lds_heads[0]);
       __syncthreads();
     }
-    head_bits(lds_heads[0], hb);
-    const ItA wagg = tile_scan(v, hb, excl);
+    hb = head_bits(lds_heads[0]);
+    const ItA wagg = tile_scan(v, hb, excl, quiet);
     if (lane == 0) lds_wave[wave] = wagg;
     __syncthreads();
     for (int w = 0; w < wave; ++w) wp = IA::comb(lds_wave[w], wp);
@@ -400,12 +427,23 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
     for (int u = 0; u < U; ++u) {
       ItA run = to_acc(IC::comb(to_ch(IA::comb(excl[u], wp)), Pt));
       OE o;
+      if (!SEG || ((quiet >> u) & 1u) != 0u) {
+        A rv = IA::val(run);
 #pragma unroll
-      for (int k = 0; k < V; ++k) {
-        const bool h = ((hb[u] >> k) & 1u) != 0;
-        const A before = h ? R::identity() : IA::val(run);
-        run = IA::comb(IA::make(R::convert(lane_elem<T>(v[u], k)), h), run);
-        o.e[k] = R::finalize(ex ? before : IA::val(run));
+        for (int k = 0; k < V; ++k) {
+          const A before = rv;
+          rv = IP::comb(R::convert(lane_elem<T>(v[u], k)), rv);
+          o.e[k] = R::finalize(ex ? before : rv);
+        }
+      } else {
+        const uint32_t pb = piece_bits(hb, u);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const bool h = ((pb >> k) & 1u) != 0;
+          const A before = h ? R::identity() : IA::val(run);
+          run = IA::comb(IA::make(R::convert(lane_elem<T>(v[u], k)), h), run);
+          o.e[k] = R::finalize(ex ? before : IA::val(run));
+        }
       }
       const int64_t base = t0 + ((int64_t)(wave * U + u) * 64 + lane) * V;
       if (whole) {
@@ -427,8 +465,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
     // The next tile: its scan and aggregate, published at once.
     if constexpr (SEG) __syncthreads();  // its run starts are marked
     if (tn < a.ntiles) {
-      head_bits(lds_heads[SEG ? nx : 0], hb);
-      const ItA wagg = tile_scan(vn, hb, excl);
+      hb = head_bits(lds_heads[SEG ? nx : 0]);
+      const ItA wagg = tile_scan(vn, hb, excl, quiet);
       if (lane == 0) lds_wave[wave] = wagg;
     }
     __syncthreads();
