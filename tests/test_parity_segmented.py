@@ -131,6 +131,35 @@ def test_segmented_one_segment_over_every_work_group(block):
         rd.config_force("segmented", None)
 
 
+@pytest.mark.parametrize("block,unroll,windows", [(64, 2, 70_000), (512, 2, 70_000), (1024, 2, 70_000),
+                                                   (256, 4, 20_000)])
+def test_segmented_window_boundaries(block, unroll, windows):
+    # Segment ends on, just before and just after the edges of windows (64 x U
+    # vectors, dealt round-robin to a work-group's wavefronts) and of rounds
+    # (one window per wavefront), over enough data that every work-group runs
+    # several batches: covers a wavefront carrying a segment's elements from
+    # one of its windows to its next, and the in-order join of window pieces.
+    wb = block // 64
+    win = 64 * unroll * 4  # int32 / float32 elements per window
+    rng = np.random.default_rng(block + unroll)
+    base = [win, win - 1, 1, win + 1, wb * win, wb * win - 1, 2, wb * win + 1, (wb + 1) * win, 3 * win - 5, 0, 7,
+            (wb - 1) * win + 3 if wb > 1 else 5, 64 * wb * win + 11]
+    lens = []
+    while sum(lens) < windows * win:  # 70,000 windows: > 256 per work-group, several join batches
+        lens.extend(base[i] for i in rng.permutation(len(base)))
+        lens.extend(int(v) for v in rng.integers(0, 3 * win, 20))
+    off = W.offsets_from_lengths(np.array(lens, np.int64))
+    x_np = W.plain(int(off[-1]), "int32", "sum", salt=21)
+    xf = W.segmented_values(int(off[-1]), "sum", salt=22)
+    try:
+        rd.config_force("segmented", dict(block=block, unroll=unroll, blocks_per_cu=1, nontemporal=1, layout=0))
+        run(x_np, off, "sum", "int32")
+        run(x_np, off, "xor", "int32", pad=1)
+        run(xf, off, "sum", "float32", pad=3)
+    finally:
+        rd.config_force("segmented", None)
+
+
 def test_segmented_long_segments_span_many_wavefronts():
     lens = np.array([1, 2 ** 22, 5, 2 ** 22 - 1, 3, 2 ** 21 + 17], np.int64)
     off = W.offsets_from_lengths(lens)
