@@ -195,9 +195,9 @@ std::vector<TuneEntry> builtin_table() {
       t.push_back({RD_KIND_COMPENSATED, es, oc, 0, 17, {256, 2, 4, 0, 0}});
       t.push_back({RD_KIND_COMPENSATED, es, oc, 18, 23, {256, 4, 2, 0, 1}});
       t.push_back({RD_KIND_COMPENSATED, es, oc, 24, 62, {256, 8, 1, 1, 1}});
-      // segmented: 16-byte windows of 4 loads per lane (2 for 16-bit data, whose 8 elements per
-      // load would otherwise need 32 accumulators)
-      t.push_back({RD_KIND_SEGMENTED, es, oc, 0, 62, {1024, es == 2 ? 2 : 4, 1, 1, 0}});
+      // segmented: windows of 4 loads per lane (2 for 16-bit data, whose 8 elements per load
+      // would otherwise need 32 accumulators), 16 wavefronts per CU
+      t.push_back({RD_KIND_SEGMENTED, es, oc, 0, 62, {es == 8 ? 1024 : 512, es == 2 ? 2 : 4, es == 8 ? 1 : 2, 1, 0}});
     }
   // Row-wise (float32), measured at 4096 x 262144: the forward streams best
   // with non-temporal loads, the write-only backward with non-temporal stores.
