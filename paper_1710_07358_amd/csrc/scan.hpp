@@ -254,7 +254,9 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   __shared__ int64_t lds_next[2];
   __shared__ uint32_t lds_heads[SEG ? 2 : 1][HW];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The wavefront index is the same in every lane; saying so keeps the
+  // tile bookkeeping in scalar registers.
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int B = blockDim.x, W = B >> 6;
   const int64_t TE = (int64_t)B * U * V;
   const uint32_t tag = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
