@@ -103,6 +103,44 @@ struct ProdAcc {  // chunk-level product state (16 bytes, combinable by DPP)
 // whole numbers of steps.
 template <int S> constexpr int64_t row_step() { return (int64_t)kRowBlock * 4 * S; }
 
+// Walk columns [cb, ce) of a row in steps (cb a multiple of the step; ce a
+// multiple of it or the row's end): body(v, c0, full) folds the step at c0.
+// Whole steps are software-pipelined -- the next step's loads are issued
+// before the current one is folded -- and use unguarded loads; only a ragged
+// last step takes the guarded path, filling missing columns with `fill`.
+template <bool AL, bool NT, int S, class Body>
+__device__ __forceinline__ void walk_steps(const float* __restrict__ row, int64_t cb, int64_t ce, int64_t cols,
+                                           float fill, int t, Body body) {
+  constexpr int64_t STEP = row_step<S>();
+  int64_t c0 = cb;
+  if (c0 + STEP <= ce) {
+    float cur[S][4], nxt[S][4];
+#pragma unroll
+    for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, true, fill, cur[u]);
+    for (; c0 + STEP <= ce; c0 += STEP) {
+      const bool more = c0 + 2 * STEP <= ce;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+          load_stripe<AL, NT>(row, c0 + STEP + ((int64_t)u * kRowBlock + t) * 4, cols, true, fill, nxt[u]);
+      }
+      body(cur, c0, true);
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) cur[u][e] = nxt[u][e];
+      }
+    }
+  }
+  if (c0 < ce) {
+    float v[S][4];
+#pragma unroll
+    for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, false, fill, v[u]);
+    body(v, c0, false);
+  }
+}
+
 template <Op O, bool AL, int S, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restrict__ x, int64_t rows,
                                                             int64_t cols, float* __restrict__ y,
@@ -110,7 +148,6 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
   constexpr int64_t STEP = row_step<S>();
   static_assert(kChunk % STEP == 0, "a chunk is a whole number of steps");
   const int t = threadIdx.x;
-  const int64_t nsteps = (cols + STEP - 1) / STEP;
   __shared__ float lds_f[kRowWaves];
   __shared__ uint64_t lds_u[kRowWaves];
   __shared__ ProdAcc lds_p[kRowWaves];
@@ -123,17 +160,12 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       for (int u = 0; u < S; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[u][e] = 0.0f;
-      for (int64_t st = 0; st < nsteps; ++st) {
-        const int64_t c0 = st * STEP;
-        const bool full = c0 + STEP <= cols;
-        float v[S][4];
-#pragma unroll
-        for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 0.0f, v[u]);
+      walk_steps<AL, NT, S>(row, 0, cols, cols, 0.0f, t, [&](const float (&v)[S][4], int64_t, bool) {
 #pragma unroll
         for (int u = 0; u < S; ++u)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[u][e] += v[u][e];
-      }
+      });
       float mine = 0.0f;
 #pragma unroll
       for (int u = 0; u < S; ++u)
@@ -151,12 +183,8 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       // first occurrence is kept; once a NaN is in, the slot stops updating.
       float best[S][4];
       int32_t at[S][4];
-      for (int64_t st = 0; st < nsteps; ++st) {
-        const int64_t c0 = st * STEP;
-        const bool full = c0 + STEP <= cols;
-        float v[S][4];
-#pragma unroll
-        for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, ident, v[u]);
+      walk_steps<AL, NT, S>(row, 0, cols, cols, ident, t, [&](const float (&v)[S][4], int64_t c0, bool full) {
+        const int64_t st = c0 / STEP;
         if (st == 0) {
 #pragma unroll
           for (int u = 0; u < S; ++u)
@@ -179,7 +207,7 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
               best[u][e] = nb;
             }
         }
-      }
+      });
       // Pack (key, column) so one unsigned max/min picks the extreme and, among
       // equal keys, the lowest column.
       uint64_t mine = MAX ? 0ull : ~0ull;
@@ -222,11 +250,8 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       for (int64_t k = 0; k < nch; ++k) {
         double p = 1.0;
         int32_t z = 0, fz = INT32_MAX;
-        for (int64_t c0 = k * kChunk; c0 < (k + 1) * kChunk && c0 < cols; c0 += STEP) {
-          const bool full = c0 + STEP <= cols;
-          float v[S][4];
-#pragma unroll
-          for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 1.0f, v[u]);
+        const int64_t ce = (k + 1) * kChunk < cols ? (k + 1) * kChunk : cols;
+        walk_steps<AL, NT, S>(row, k * kChunk, ce, cols, 1.0f, t, [&](const float (&v)[S][4], int64_t c0, bool) {
 #pragma unroll
           for (int u = 0; u < S; ++u)
 #pragma unroll
@@ -237,7 +262,7 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
               const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
               fz = (zero && col < fz) ? col : fz;
             }
-        }
+        });
         const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0, INT32_MAX}, comb, lds_p);
         if (t == 0) {
           chunk_prod[r * nch + k] = (float)tot.p;
