@@ -91,6 +91,27 @@ def test_rowwise_shapes(op, shape):
     run_rows(x, op, pad=True)
 
 
+@pytest.mark.parametrize("op", OPS)
+def test_rowwise_every_step_width(op):
+    # The forward walks a row in steps of 1024 x S columns (whole steps
+    # pipelined, one ragged step guarded); the launch table may pick any S.
+    # Widths: below one step, one whole step, whole steps plus one column, and
+    # a product chunk (16,384 columns) plus a ragged remainder.
+    rng = np.random.default_rng(31)
+    try:
+        for S in (1, 2, 4, 8):
+            rd.config_force("rowwise", dict(block=256, unroll=S, blocks_per_cu=2, nontemporal=S % 2, layout=0))
+            for cols in (1000, 1024 * S, 3 * 1024 * S + 1, 16384 + 1024 * S + 7):
+                shape = (3, cols)
+                x = (rng.uniform(0.99, 1.01, size=shape) if op == "prod" else rng.standard_normal(shape)).astype(np.float32)
+                if op == "prod":
+                    x[1, cols // 2] = 0.0  # one zero: the backward's single-zero rule
+                run_rows(x, op)
+                run_rows(x, op, pad=True)
+    finally:
+        rd.config_force("rowwise", None)
+
+
 @pytest.mark.parametrize("op", ["max", "min"])
 def test_rowwise_ties_lowest_index(op):
     rng = np.random.default_rng(3)
