@@ -359,7 +359,7 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
   };
 
   // ---- the rounds
-  int64_t wi = wfirst + wib;  // this wavefront's window in round 0
+  int64_t wi = wfirst + wib;  // this wavefront's first window
   u32x4 cur[U], nxt[U];
   if (wi < wlast) {
     if (wi * P.win < P.nvec) load_window(wi, cur);
