@@ -24,9 +24,9 @@ struct Launch {
 // launches, and so are the counters.
 struct Scratch {
   unsigned* ticket;     // [0]: completion counter; [1]: status (nonzero: a bounded wait ran out)
-  unsigned* counters;   // segmented: one per wavefront
+  unsigned* counters;   // segmented: one per work-group
   uint64_t* partial;    // kPartialWords words per work-group
-  uint64_t* carry;      // segmented: kCarryWords words per slot, 2 slots per wavefront
+  uint64_t* carry;      // segmented: kCarryWords words per slot, 2 slots per work-group
   int64_t partial_cap;  // work-groups
   int64_t carry_cap;    // carry slots
   void* design;         // paper-design baselines: plain partials (kDesignBytes)
