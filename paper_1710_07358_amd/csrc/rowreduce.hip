@@ -252,16 +252,29 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
         int32_t z = 0, fz = INT32_MAX;
         const int64_t ce = (k + 1) * kChunk < cols ? (k + 1) * kChunk : cols;
         walk_steps<AL, NT, S>(row, k * kChunk, ce, cols, 1.0f, t, [&](const float (&v)[S][4], int64_t c0, bool) {
+          // A zero multiplies as 1.0 (exactly p), so the product needs no
+          // 64-bit select; zeros are counted, and the first located, only in
+          // the steps where some lane of the wavefront holds one.
+          bool anyz = false;
 #pragma unroll
           for (int u = 0; u < S; ++u)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const bool zero = (v[u][e] == 0.0f);
-              p = zero ? p : p * (double)v[u][e];
-              z += zero ? 1 : 0;
-              const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
-              fz = (zero && col < fz) ? col : fz;
+              anyz = anyz || zero;
+              p *= (double)(zero ? 1.0f : v[u][e]);
             }
+          if (__builtin_amdgcn_ballot_w64(anyz) != 0ull) {
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const bool zero = (v[u][e] == 0.0f);
+                z += zero ? 1 : 0;
+                const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
+                fz = (zero && col < fz) ? col : fz;
+              }
+          }
         });
         const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0, INT32_MAX}, comb, lds_p);
         if (t == 0) {
