@@ -64,7 +64,7 @@ def time_launches(fn, steps: int, warmup: int, torch) -> float:
     return start.elapsed_time(stop) / 1e3 / steps
 
 
-def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
+def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte, launch_loop=True):
     lens = W.segment_lengths()
     off = W.offsets_from_lengths(lens)
     n = int(off[-1])
@@ -106,7 +106,7 @@ def bench_segmented(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
                 assert got[sidx] == oracle.reduce(seg, "max", "float32"), sidx
         t = min(eager, replay)
         per_seg = None
-        if op == "sum":
+        if op == "sum" and launch_loop:
             # baseline: one plain launch per segment (65,536 launches), eager and graph-captured
             outs = torch.empty(nseg, dtype=torch.float32, device=dev)
             views = [x[int(off[i]):int(off[i + 1])] for i in range(nseg)]
@@ -392,6 +392,8 @@ def main() -> int:
     ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs", "shard"],
                     default=None,
                     help="run one secondary workload alone (for profiling) and print its results")
+    ap.add_argument("--no-launch-loop", action="store_true",
+                    help="skip the one-launch-per-segment baseline (65,536 launches; for counter runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the HBM-traffic summary of two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -429,7 +431,8 @@ def main() -> int:
         if args.only == "scan":
             res = bench_scan(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb)
         elif args.only == "segmented":
-            res = bench_segmented(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb)
+            res = bench_segmented(rd, W, oracle, torch, np, args.steps, args.warmup, plain_spb,
+                                  launch_loop=not args.no_launch_loop)
         elif args.only == "rowwise":
             res = bench_rowwise(rd, torch, args.steps, args.warmup, plain_spb)
         elif args.only == "paper_designs":
