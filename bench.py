@@ -260,6 +260,18 @@ def bench_scan(rd, W, oracle, torch, np, steps, warmup, plain_s_per_byte):
     return res
 
 
+def bench_argreduce(rd, torch, x, steps, warmup):
+    """Maximum and the lowest index attaining it over the 2^28 float32 input,
+    checked against torch (value equal to the maximum, no earlier index
+    holding it)."""
+    t = time_launches(lambda: rd.argreduce(x, "max"), steps, warmup, torch)
+    tv, ti = rd.argreduce(x, "max")
+    v, i = float(tv.item()), int(ti.item())
+    ok = v == float(x.max().item()) and float(x[i].item()) == v and not bool((x[:i] == v).any().item())
+    return {"op": "max", "ms": round(t * 1e3, 4), "GBps": round(gbps(4 * x.numel(), t), 1), "index": i,
+            "pass": ok}
+
+
 def bench_shard(rd, torch, steps, warmup):
     """One GPU's share of the 8-way sharded headline: 2^25 float32 (128 MiB).
     It fits the 256 MB MALL, so the cold figure rotates over 4 such buffers
@@ -389,7 +401,8 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true", help="skip the precision error table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of the 1 GiB input (counter calibration)")
-    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs", "shard"],
+    ap.add_argument("--only", choices=["compensated", "segmented", "rowwise", "scan", "paper_designs", "shard",
+                                       "argreduce"],
                     default=None,
                     help="run one secondary workload alone (for profiling) and print its results")
     ap.add_argument("--no-launch-loop", action="store_true",
@@ -439,6 +452,9 @@ def main() -> int:
             res = bench_paper_designs(rd, torch, args.steps, args.warmup)
         elif args.only == "shard":
             res = bench_shard(rd, torch, args.steps, args.warmup)
+        elif args.only == "argreduce":
+            xa = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
+            res = bench_argreduce(rd, torch, xa, args.steps, args.warmup)
         else:
             x = torch.from_numpy(W.plain(n, "float32", "sum", config=1, salt=28)).to(dev)
             outc = torch.empty((), dtype=torch.float64, device=dev)
@@ -492,6 +508,8 @@ def main() -> int:
             ec = abs(float(outc.item()) - check["exact"])
             secondary["compensated"].update({"abs_err": ec, "err_over_abs_sum": ec / check["abs_sum"],
                                              "pass": ec <= 2.0 ** -40 * check["abs_sum"]})
+        log("arg-reduction")
+        secondary["argreduce"] = bench_argreduce(rd, torch, x, args.steps, args.warmup)
         del x
         torch.cuda.empty_cache()
         log("segmented")
