@@ -335,9 +335,18 @@ int orc_exact_sum(const void* x, int64_t n, int dtype, double* sum, double* abs_
 
 typedef struct { double hi, lo; } dd;
 
-/* (hi + lo) * b with the exact product hi*b recovered by fma. */
+/* (hi + lo) * b with the exact product hi*b recovered by fma.
+ *
+ * A zero, infinite or NaN leading product is returned as it stands, with a
+ * zero tail: it is then the IEEE product itself (the sign of a zero is the
+ * exclusive-or of the factors' signs), and the error-free step, whose sum
+ * p + e would turn -0 into +0 and inf - inf into NaN, does not apply. */
 static dd dd_mul_double(dd a, double b) {
     double p = a.hi * b;
+    if (p == 0.0 || !isfinite(p)) {
+        dd z = { p, 0.0 };
+        return z;
+    }
     double e = fma(a.hi, b, -p); /* exact rounding error of a.hi*b */
     e = fma(a.lo, b, e);
     double s = p + e;
@@ -348,6 +357,10 @@ static dd dd_mul_double(dd a, double b) {
 
 static dd dd_mul(dd a, dd b) {
     double p = a.hi * b.hi;
+    if (p == 0.0 || !isfinite(p)) {
+        dd z = { p, 0.0 };
+        return z;
+    }
     double e = fma(a.hi, b.hi, -p);
     e += a.hi * b.lo + a.lo * b.hi;
     double s = p + e;
@@ -356,11 +369,15 @@ static dd dd_mul(dd a, dd b) {
     return r;
 }
 
+/* The double nearest hi + lo.  A zero tail leaves hi untouched, so a signed
+ * zero keeps its sign (-0 + +0 would round to +0). */
+static double dd_value(dd a) { return a.lo == 0.0 ? a.hi : a.hi + a.lo; }
+
 int orc_prod(const void* x, int64_t n, int dtype, double* out) {
     if (!is_float_dtype(dtype) || n < 0) return -1;
     dd acc = { 1.0, 0.0 };
     for (int64_t i = 0; i < n; ++i) acc = dd_mul_double(acc, orc_load_float(x, i, dtype));
-    *out = acc.hi + acc.lo;
+    *out = dd_value(acc);
     return 0;
 }
 
@@ -529,7 +546,7 @@ static void scan_emit(scan_state* st, void* out, int64_t i) {
         else if (st->sum_pinf) r = INFINITY;
         else if (st->sum_ninf) r = -INFINITY;
         ((double*)out)[i] = r;
-    } else if (st->op == OP_PROD) ((double*)out)[i] = st->prod.hi + st->prod.lo;
+    } else if (st->op == OP_PROD) ((double*)out)[i] = dd_value(st->prod);
     else ((double*)out)[i] = st->ext;
 }
 
@@ -627,7 +644,7 @@ int orc_row_grad(const float* x, int64_t rows, int64_t cols, int op, const doubl
             dd prefix = { 1.0, 0.0 }; /* product of x[0..j) */
             for (int64_t j = 0; j < cols; ++j) {
                 dd t = dd_mul_double(dd_mul(prefix, suffix[j + 1]), g[r]);
-                gr[j] = t.hi + t.lo;
+                gr[j] = dd_value(t);
                 prefix = dd_mul_double(prefix, (double)row[j]);
             }
         } else return -1;

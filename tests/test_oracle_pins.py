@@ -123,6 +123,67 @@ def test_int_brute_force_all_orders():
         assert len(results) == 1, op
 
 
+# ------------------------------------------------ 16-bit bit patterns (and/or/xor on float16, bfloat16)
+
+@pytest.mark.parametrize("dtype", ["float16", "bfloat16"])
+def test_bitwise_16bit_planted_bits(dtype):
+    # and over all-ones patterns with planted cleared bits gives exactly the
+    # bits never cleared; or over zeros with planted set bits gives the plants
+    rng = np.random.default_rng(41)
+    n = 5000
+    allones = np.full(n, 0xFFFF, np.uint16)
+    cleared = 0
+    for bit in rng.choice(16, size=6, replace=False):
+        allones[rng.integers(0, n)] &= np.uint16(~(1 << int(bit)) & 0xFFFF)
+        cleared |= 1 << int(bit)
+    assert oracle.reduce(allones, "and", dtype) == 0xFFFF & ~cleared
+    zeros = np.zeros(n, np.uint16)
+    planted = 0
+    for bit in rng.choice(16, size=5, replace=False):
+        zeros[rng.integers(0, n)] |= np.uint16(1 << int(bit))
+        planted |= 1 << int(bit)
+    assert oracle.reduce(zeros, "or", dtype) == planted
+    # the neutral elements are 16 bits wide
+    assert oracle.identity("and", dtype) == 0xFFFF
+    assert oracle.identity("or", dtype) == 0 and oracle.identity("xor", dtype) == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 1000, 65_536])
+def test_bitwise_16bit_xor_closed_form(n):
+    x = np.arange(n, dtype=np.uint32).astype(np.uint16)
+    assert oracle.reduce(x, "xor", "float16") == _xor_prefix(n - 1)
+    assert oracle.reduce(x, "xor", "bfloat16") == _xor_prefix(n - 1)
+
+
+def test_bitwise_16bit_vs_python_ints():
+    import functools
+    import operator
+    rng = np.random.default_rng(42)
+    x = rng.integers(0, 1 << 16, size=3001).astype(np.uint16)
+    ints = [int(v) for v in x]
+    for op, f, ident in (("and", operator.and_, 0xFFFF), ("or", operator.or_, 0), ("xor", operator.xor, 0)):
+        expect = functools.reduce(f, ints, ident)
+        assert oracle.reduce(x, op, "bfloat16") == expect
+        # running values (scan), inclusive and exclusive, and per segment
+        run = list(__import__("itertools").accumulate(ints, f))
+        inc = oracle.scan(x, op, "float16")
+        exc = oracle.scan(x, op, "float16", exclusive=True)
+        assert inc.tolist() == run
+        assert exc.tolist() == [ident] + run[:-1]
+        off = np.array([0, 0, 17, 1000, 1000, 3001])
+        seg = oracle.segmented(x, off, op, "bfloat16")
+        for s in range(5):
+            assert int(seg[s]) == functools.reduce(f, ints[off[s]:off[s + 1]], ident), (op, s)
+
+
+def test_bitwise_16bit_scan_xor_closed_form():
+    # xor scan of 0..n-1 as 16-bit patterns: position i holds xor(0..i)
+    n = 4099
+    x = np.arange(n, dtype=np.uint16)
+    inc = oracle.scan(x, "xor", "bfloat16")
+    assert all(int(inc[i]) == _xor_prefix(i) for i in range(n))
+
+
 def test_identities():
     # neutral elements: value of the reduction over no elements
     assert oracle.identity("sum", "int32") == 0
@@ -276,6 +337,43 @@ def test_prod_vs_fraction():
 def test_prod_zero_and_sign():
     assert oracle.reduce(np.array([2.0, 0.0, 5.0]), "prod") == 0.0
     assert oracle.reduce(np.array([-2.0, 3.0]), "prod") == -6.0
+
+
+# IEEE 754: the sign of a product (zeros and infinities included) is the
+# exclusive-or of the factors' signs; inf * 0 is NaN.  Python's own float
+# multiplication is IEEE binary64, so math.prod of a few exactly
+# representable factors is the expected value, sign bit included.
+SIGNED_ZERO_CASES = [
+    [-0.0], [0.0], [-2.0, 0.0], [-0.0, 2.0], [-0.0, -2.0], [0.0, -0.0], [-0.0, -0.0],
+    [3.0, -0.0, 5.0, -1.0], [-1.0, 0.0, -1.0, -0.0, 7.0], [-math.inf, 2.0], [math.inf, -0.5, -4.0],
+    [math.inf, 0.0], [-0.0, math.inf], [1e300, 1e300], [-1e300, 1e300], [1e-300, -1e-300],
+]
+
+
+def _same_bits(a, b):
+    if math.isnan(a) or math.isnan(b):
+        return math.isnan(a) and math.isnan(b)
+    return a == b and math.copysign(1.0, a) == math.copysign(1.0, b)
+
+
+@pytest.mark.parametrize("vals", SIGNED_ZERO_CASES, ids=lambda v: ",".join(map(repr, v)))
+def test_prod_signed_zero_and_infinity(vals):
+    expect = math.prod(vals)
+    got = oracle.reduce(np.array(vals, np.float64), "prod")
+    assert _same_bits(got, expect), (vals, got, expect)
+    if all(v == 0 or math.isinf(v) or abs(v) in (0.5, 1.0, 2.0, 3.0, 4.0, 5.0, 7.0) for v in vals):
+        # the same factors stored as float32, float16 and bfloat16 (all exact)
+        f32 = np.array(vals, np.float32)
+        assert _same_bits(oracle.reduce(f32, "prod", "float32"), expect)
+        assert _same_bits(oracle.reduce(f32.astype(np.float16), "prod", "float16"), expect)
+        bf = (f32.view(np.uint32) >> 16).astype(np.uint16)
+        assert _same_bits(oracle.reduce(bf, "prod", "bfloat16"), expect)
+    # running products carry the same signs, and so does every segment
+    run = oracle.scan(np.array(vals, np.float64), "prod", "float64")
+    for i in range(len(vals)):
+        assert _same_bits(run[i], math.prod(vals[: i + 1])), (vals, i)
+    seg = oracle.segmented(np.array(vals * 2, np.float64), np.array([0, len(vals), 2 * len(vals)]), "prod")
+    assert _same_bits(seg[0], expect) and _same_bits(seg[1], expect)
 
 
 # ---------------------------------------------------------------- float min / max
