@@ -114,6 +114,35 @@ rd_status rd_workspace_destroy(rd_workspace* ws);
  * launch that failed part-way). */
 rd_status rd_workspace_reset(rd_workspace* ws, void* stream);
 
+/* Bits of rd_workspace_status. */
+typedef enum rd_wait_flags {
+    RD_WAIT_GRID = 1, /* a grid-stage wait of rd_reduce, rd_reduce_compensated, rd_argreduce or a
+                         segment-carry wait of rd_segmented_reduce ran out */
+    RD_WAIT_SCAN = 2  /* a look-back wait of rd_scan / rd_segmented_scan ran out */
+} rd_wait_flags;
+
+/* Outcome of the bounded waits inside the kernels.  Stage 2 of Section 2.3
+ * (the partial results of every work-group combined by one of them) and the
+ * scan's tile prefixes run inside a single launch here, so a work-group waits
+ * for values other work-groups publish; every such wait is bounded, and a
+ * correct launch never comes close to the bound.  A wait that runs out sets a
+ * status word in the workspace; the launch then ends normally but its result
+ * is unspecified.
+ *   ws    : one workspace, or NULL for every workspace (default and explicit)
+ *           of the current device
+ *   flags : out; rd_wait_flags bits of the words found set
+ * Synchronises the device (so it must not be called during graph capture),
+ * reads the words and clears them.  Returns RD_ERR_WORKSPACE if ws belongs to
+ * another device. */
+rd_status rd_workspace_status(rd_workspace* ws, unsigned* flags);
+
+/* Test hook for the failure path of the bounded waits.  While `on` is
+ * nonzero, every rd_reduce and rd_scan launch adds one wait for a slot that
+ * nothing publishes: the wait runs out (after its bound; about a second for
+ * rd_reduce), rd_workspace_status then reports it, and the kernel still ends
+ * normally (with an unspecified result).  Not for production use. */
+rd_status rd_debug_force_wait_timeout(int on);
+
 /* Element size in bytes of a dtype (0 for an invalid value). */
 size_t rd_dtype_size(rd_dtype dt);
 
@@ -145,7 +174,11 @@ rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
 rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out,
                                 rd_workspace* ws, void* stream);
 
-/* Minimum or maximum together with the LOWEST index attaining it, one launch.
+/* Minimum or maximum together with the LOWEST index attaining it, one launch:
+ * the min and max combiners of Section 1.1 applied to (value, index) pairs,
+ * where the pair with the smaller index wins a tie (an associative and
+ * commutative combiner, so the grid of Section 2.3 and Section 2.5 applies
+ * unchanged).
  *   dt        : any dtype;  op : RD_MIN or RD_MAX (else RD_ERR_UNSUPPORTED)
  *   value_out : device pointer to one element of dtype dt -- exactly the
  *               stored element at *index_out
@@ -172,8 +205,11 @@ rd_status rd_reduce_paper_design(const void* x, int64_t n, rd_dtype dt, int vari
 
 /* ---- segmented reduction ------------------------------------------------- */
 
-/* out[s] = x[offsets[s]] (+) ... (+) x[offsets[s+1]-1] for s in [0, nseg),
- * all segments in ONE persistent launch (capturable in a HIP graph).
+/* out[s] = x[offsets[s]] (+) ... (+) x[offsets[s+1]-1] for s in [0, nseg):
+ * the reduction of Section 1.1 applied to every segment, all segments in ONE
+ * persistent launch (Section 2.5: persistent threads suit irregular work and
+ * avoid returning control to the host between pieces of work; capturable in
+ * a HIP graph).
  *   offsets : device int64 array of nseg+1 non-decreasing entries; only
  *             x[offsets[0] .. offsets[nseg]) is read
  *   out     : device array of nseg elements of rd_out_dtype(dt, op)
@@ -208,7 +244,8 @@ rd_status rd_segmented_reduce(const void* x, const int64_t* offsets, int64_t nse
 rd_status rd_scan(const void* x, int64_t n, rd_dtype dt, rd_op op, int exclusive, void* out,
                   rd_workspace* ws, void* stream);
 
-/* Scan restarted at every segment start.  With the CSR offsets of nseg
+/* Scan restarted at every segment start (the prefix form of Section 1.1's
+ * reduction, per segment; one persistent launch as in Section 2.5).  With the CSR offsets of nseg
  * segments (noffsets = nseg + 1 non-decreasing entries, offsets[0] = 0,
  * offsets[nseg] = n), out[i] for offsets[s] <= i < offsets[s+1] reduces
  * x[offsets[s] .. i] (inclusive) or x[offsets[s] .. i) (exclusive; the neutral
@@ -225,12 +262,14 @@ rd_status rd_segmented_scan(const void* x, int64_t n, const int64_t* offsets, in
 
 /* ---- row-wise reduction and its gradient --------------------------------- */
 
-/* Bytes of the `saved` buffer rd_rowreduce_fwd fills for rd_rowreduce_bwd:
+/* Bytes of the `saved` buffer rd_rowreduce_fwd fills for rd_rowreduce_bwd
+ * (the state the gradient of the Section 1.1 reduction of each row needs):
  * 0 for sum, 8*rows (lowest extreme index) for min/max, and per-row zero
- * bookkeeping plus per-chunk products for product. */
+ * bookkeeping plus per-tile products for product. */
 size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols);
 
-/* y[r] = x[r,0] (+) ... (+) x[r,cols-1] for a row-major float32 matrix.
+/* y[r] = x[r,0] (+) ... (+) x[r,cols-1] for a row-major float32 matrix: the
+ * reduction of Section 1.1 (+, max, min, x) over every row, one launch.
  *   dt    : RD_F32;  op : RD_SUM, RD_MAX, RD_MIN or RD_PROD
  *   y     : device float32[rows]
  *   saved : device buffer of rd_saved_bytes(op, rows, cols) bytes (may be
@@ -240,7 +279,11 @@ size_t rd_saved_bytes(rd_op op, int64_t rows, int64_t cols);
 rd_status rd_rowreduce_fwd(const void* x, int64_t rows, int64_t cols, rd_dtype dt, rd_op op,
                            void* y, void* saved, void* stream);
 
-/* grad_in[r,j] = d y[r] / d x[r,j] * g[r]:
+/* grad_in[r,j] = d y[r] / d x[r,j] * g[r], the derivative of the row-wise
+ * reduction of Section 1.1 (the paper defines the forward only; the
+ * derivative follows from each combiner: d(sum)/dx = 1, d(max)/dx = 1 at
+ * the first position attaining it, d(prod)/dx_j = the product of the
+ * other entries):
  *   sum     -> g[r] everywhere;
  *   min/max -> g[r] at the saved lowest extreme index, 0 elsewhere;
  *   product -> g[r] * prod_{i != j} x[r,i], formed from prefix and suffix

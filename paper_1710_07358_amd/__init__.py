@@ -6,7 +6,8 @@ The binding is imported on first use, so ``paper_1710_07358_amd.workloads``
 """
 _API = ("reduce", "reduce_compensated", "argreduce", "reduce_paper_design", "segmented", "scan", "rowreduce", "rowreduce_forward",
         "rowreduce_backward", "RowReduce", "Workspace", "out_dtype", "saved_bytes",
-        "config_get", "config_force", "tune_load", "DTYPES", "OPS")
+        "config_get", "config_force", "tune_load", "workspace_status", "debug_force_wait_timeout",
+        "DTYPES", "OPS")
 
 
 def __getattr__(name):

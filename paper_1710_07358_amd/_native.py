@@ -21,6 +21,7 @@ RD_OK, RD_ERR_INVALID_ARG, RD_ERR_UNSUPPORTED, RD_ERR_HIP, RD_ERR_NOMEM, RD_ERR_
     0, -1, -2, -3, -4, -5, -6)
 (RD_KIND_PLAIN, RD_KIND_COMPENSATED, RD_KIND_SEGMENTED, RD_KIND_ROWWISE, RD_KIND_ROWWISE_BWD, RD_KIND_SCAN,
  RD_KIND_SEGMENTED_SCAN) = range(7)
+RD_WAIT_GRID, RD_WAIT_SCAN = 1, 2
 
 STATUS_NAMES = {0: "RD_OK", -1: "RD_ERR_INVALID_ARG", -2: "RD_ERR_UNSUPPORTED", -3: "RD_ERR_HIP",
                 -4: "RD_ERR_NOMEM", -5: "RD_ERR_CAPTURE", -6: "RD_ERR_WORKSPACE"}
@@ -40,6 +41,8 @@ SIGNATURES = {
     "rd_workspace_create": (_ci, [ctypes.POINTER(_vp), _ci]),
     "rd_workspace_destroy": (_ci, [_vp]),
     "rd_workspace_reset": (_ci, [_vp, _vp]),
+    "rd_workspace_status": (_ci, [_vp, ctypes.POINTER(ctypes.c_uint)]),
+    "rd_debug_force_wait_timeout": (_ci, [_ci]),
     "rd_dtype_size": (_sz, [_ci]),
     "rd_out_dtype": (_ci, [_ci, _ci, ctypes.POINTER(_ci)]),
     "rd_reduce": (_ci, [_vp, _i64, _ci, _ci, _vp, _vp, _vp]),

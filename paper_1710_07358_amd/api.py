@@ -90,6 +90,21 @@ class Workspace:
             pass
 
 
+def workspace_status(workspace: "Workspace | None" = None) -> int:
+    """Wait-status bits (RD_WAIT_GRID = 1, RD_WAIT_SCAN = 2) of one workspace,
+    or of every workspace of the current device; reading clears them.
+    Synchronises the device."""
+    flags = ctypes.c_uint(0)
+    N.check(N.lib().rd_workspace_status(_ws(workspace), ctypes.byref(flags)))
+    return int(flags.value)
+
+
+def debug_force_wait_timeout(on: bool) -> None:
+    """Failure-path test hook: while on, reduce() and scan() launches run one
+    bounded wait out (their results are then unspecified)."""
+    N.check(N.lib().rd_debug_force_wait_timeout(1 if on else 0))
+
+
 def reduce(x: torch.Tensor, op: str, out: torch.Tensor | None = None, workspace: Workspace | None = None,
            n: int | None = None) -> torch.Tensor:
     """x[0] (op) ... (op) x[n-1] over a contiguous device tensor (0-d result).

@@ -53,6 +53,12 @@ def build(jobs: int | None = None) -> str:
     """Compile every HIP/C++ source and link librd.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    # objects no current source produces (an older source layout) are removed,
+    # so _build/ holds exactly what is linked
+    wanted = {os.path.basename(src) + ".o" for src in srcs}
+    for f in os.listdir(BUILD):
+        if f.endswith(".o") and f not in wanted:
+            os.remove(os.path.join(BUILD, f))
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -10,8 +10,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <utility>
 #include <vector>
@@ -89,6 +91,15 @@ size_t workspace_bytes() {
   return counters_bytes() + partial_bytes() + carry_bytes() + (size_t)rd::kDesignBytes + scan_bytes();
 }
 
+// Every live workspace (default and explicit), for rd_workspace_status; its
+// own lock (workspaces are created while g_mu is held).
+std::mutex g_ws_mu;
+std::set<rd_workspace*> g_all_ws;
+
+// Set by rd_debug_force_wait_timeout: launches of rd_reduce and rd_scan add
+// one bounded wait that runs out.
+std::atomic<int> g_probe{0};
+
 rd_status create_workspace(rd_workspace** out, int device) {
   int prev = -1;
   hipError_t e = hipGetDevice(&prev);
@@ -125,6 +136,10 @@ rd_status create_workspace(rd_workspace** out, int device) {
   s.scan_tile_first = (uint64_t*)p;
   p += round_up((size_t)rd::kScanTiles * 8, kAlign);
   s.scan_slots = (uint64_t*)p;
+  {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    g_all_ws.insert(ws);
+  }
   *out = ws;
   return RD_OK;
 }
@@ -360,7 +375,8 @@ rd_status scan_call(const char* name, const void* x, int64_t n, const int64_t* h
                 (long long)n, (long long)ntiles, (long long)tile, (long long)rd::kScanTiles);
   rd::ScanFn fn = rd::scan_launcher(dt, op, seg, unroll, cfg.nontemporal != 0);
   if (!fn) return fail(RD_ERR_UNSUPPORTED, "%s: no kernel for dtype %d op %d", name, (int)dt, (int)op);
-  const rd::Launch l{cfg.block, std::max(1, cfg.blocks_per_cu * info.cus), unroll, cfg.nontemporal != 0, 0};
+  rd::Launch l{cfg.block, std::max(1, cfg.blocks_per_cu * info.cus), unroll, cfg.nontemporal != 0, 0};
+  l.probe = g_probe.load();
   const rd::ScanCall c{x, n, out, exclusive != 0, seg ? heads : nullptr, seg ? nheads : 0};
   hipError_t e = fn(c, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, name);
@@ -403,9 +419,53 @@ rd_status rd_workspace_destroy(rd_workspace* ws) {
     for (auto it = g_default_ws.begin(); it != g_default_ws.end(); ++it)
       if (it->second == ws) return fail(RD_ERR_INVALID_ARG, "cannot destroy a default workspace");
   }
+  {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    g_all_ws.erase(ws);
+  }
   hipError_t e = hipFree(ws->mem);
   delete ws;
   return e == hipSuccess ? RD_OK : hip_fail(e, "hipFree");
+}
+
+rd_status rd_workspace_status(rd_workspace* ws, unsigned* flags) {
+  if (!flags) return fail(RD_ERR_INVALID_ARG, "rd_workspace_status: flags is NULL");
+  int dev;
+  DeviceInfo info;
+  rd_status st = current_device(&dev, &info);
+  if (st != RD_OK) return st;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "rd_workspace_status: hipDeviceSynchronize");
+  std::vector<rd_workspace*> targets;
+  if (ws) {
+    if (ws->device != dev)
+      return fail(RD_ERR_WORKSPACE, "workspace belongs to device %d, current device is %d", ws->device, dev);
+    targets.push_back(ws);
+  } else {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    for (rd_workspace* w : g_all_ws)
+      if (w->device == dev) targets.push_back(w);
+  }
+  unsigned f = 0;
+  const unsigned zero = 0;
+  for (rd_workspace* w : targets) {
+    unsigned grid_word = 0, scan_word = 0;
+    if ((e = hipMemcpy(&grid_word, w->scratch.ticket + 1, 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&scan_word, w->scratch.scan_ctl + 3, 4, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "rd_workspace_status: read");
+    if (grid_word) f |= RD_WAIT_GRID;
+    if (scan_word) f |= RD_WAIT_SCAN;
+    if ((grid_word && (e = hipMemcpy(w->scratch.ticket + 1, &zero, 4, hipMemcpyHostToDevice)) != hipSuccess) ||
+        (scan_word && (e = hipMemcpy(w->scratch.scan_ctl + 3, &zero, 4, hipMemcpyHostToDevice)) != hipSuccess))
+      return hip_fail(e, "rd_workspace_status: clear");
+  }
+  *flags = f;
+  return RD_OK;
+}
+
+rd_status rd_debug_force_wait_timeout(int on) {
+  g_probe.store(on ? 1 : 0);
+  return RD_OK;
 }
 
 rd_status rd_workspace_reset(rd_workspace* ws, void* stream) {
@@ -433,7 +493,10 @@ rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out, 
   const rd_config cfg = choose_config(RD_KIND_PLAIN, dt, op, n);
   rd::PlainFn fn = rd::plain_launcher(dt, op, cfg.unroll, cfg.nontemporal != 0);
   if (!fn) return fail(RD_ERR_UNSUPPORTED, "rd_reduce: no kernel for dtype %d op %d unroll %d", (int)dt, (int)op, cfg.unroll);
-  const rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, info.cus, (int)w->scratch.partial_cap);
+  const int probe = g_probe.load();
+  // With the probe on, slot G (one past the grid) must exist: cap the grid one lower.
+  rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, info.cus, (int)w->scratch.partial_cap - probe);
+  l.probe = probe;
   hipError_t e = fn(n > 0 ? x : out, n, out, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce launch");
 }

@@ -17,13 +17,14 @@ struct Launch {
   int unroll;
   bool nontemporal;
   int layout;  // rd_config::layout
+  int probe = 0;  // failure-path test: add one bounded wait that runs out (rd_debug_force_wait_timeout)
 };
 
 // Device scratch handed to a kernel.  Published values live in tagged
 // 64-bit words (one per 32 bits of value); every word is zero between
 // launches, and so are the counters.
 struct Scratch {
-  unsigned* ticket;     // [0]: completion counter; [1]: status (nonzero: a bounded wait ran out)
+  unsigned* ticket;     // [0]: completion counter; [1]: status (nonzero: a bounded wait ran out, sticky)
   unsigned* counters;   // segmented: one per work-group
   uint64_t* partial;    // kPartialWords words per work-group
   uint64_t* carry;      // segmented: kCarryWords words per slot, 2 slots per work-group
@@ -32,7 +33,7 @@ struct Scratch {
   void* design;         // paper-design baselines: plain partials (kDesignBytes)
   // Scans: control words, per-tile first-head index, published tile and
   // group aggregates (tagged with a launch epoch, so never cleared).
-  unsigned* scan_ctl;         // [0] epoch, [1] next tile, [2] arrivals, [3] status
+  unsigned* scan_ctl;         // [0] epoch, [1] next tile, [2] arrivals, [3] status (sticky), [4] give-up tag
   uint64_t* scan_tile_first;  // kScanTiles words
   uint64_t* scan_slots;       // kScanSlots x kScanSlotWords words
 };

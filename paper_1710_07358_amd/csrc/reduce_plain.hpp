@@ -44,7 +44,8 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
                                                       int64_t n,
                                                       uint64_t* __restrict__ partial,
                                                       unsigned* __restrict__ ticket,
-                                                      typename R::Out* __restrict__ out, int layout) {
+                                                      typename R::Out* __restrict__ out, int layout,
+                                                      int probe) {
   using T = typename R::T;
   using A = typename R::Acc;
   constexpr int V = 16 / (int)sizeof(T);
@@ -106,8 +107,10 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const typename R::T* __res
   if (tid == 0) publish(partial + blockIdx.x * SW, blk);
 
   if (arrive_last(ticket, (unsigned)G, &last_flag)) {
+    // probe (failure-path test only): also collect slot G, which no work-group
+    // publishes, so that one bounded wait runs out and sets the status word.
     A r = R::identity();
-    for (int64_t b = tid; b < G; b += B) r = R::apply(r, collect<A>(partial + b * SW, ticket + 1));
+    for (int64_t b = tid; b < G + probe; b += B) r = R::apply(r, collect<A>(partial + b * SW, ticket + 1));
     r = block_reduce(r, R::identity(), comb, lds);
     if (tid == 0) *out = R::finalize(r);
   }
@@ -202,7 +205,7 @@ hipError_t launch_plain(const void* x, int64_t n, void* out, const Scratch& ws, 
                         hipStream_t s) {
   hipLaunchKernelGGL((reduce_kernel<R, U, NT>), dim3(l.grid), dim3(l.block), 0, s,
                      (const typename R::T*)x, n, ws.partial, ws.ticket,
-                     (typename R::Out*)out, l.layout);
+                     (typename R::Out*)out, l.layout, l.probe ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -11,14 +11,18 @@
 //     column when lanes, wavefronts and slots are combined.
 //   product also records, per row, the number of exact zeros, the first
 //     zero's column and the product of the nonzero entries, and per chunk
-//     the product of its nonzero entries (the state the gradient needs).
+//     of kChunk columns the products of all chunks before it and of all
+//     chunks after it, in float64 (the state the gradient needs).
 // Backward (grad = dy/dx * g):
 //   sum     -> g[r] broadcast (write-only);
 //   max/min -> g[r] at the saved column, 0 elsewhere (write-only);
 //   product -> rows with >= 2 zeros: 0; one zero: g*prod(nonzeros) at the
-//              zero; no zero: g * prod_{i<j} x * prod_{i>j} x, built from
-//              chunk products and, inside a chunk, DPP prefix/suffix scans
-//              over wavefronts and an LDS step over wavefronts -- no division.
+//              zero; no zero: g * prod_{i<j} x * prod_{i>j} x.  One
+//              work-group per (row, chunk) over a flat grid: the chunk's own
+//              exclusive prefix and suffix products come from DPP scans over
+//              the lanes and one scan over the chunk's 64 wavefront pieces,
+//              the rest of the row from the saved chunk prefix/suffix -- no
+//              division, every tile independent.
 #include "rd_device.hpp"
 #include "rd_internal.hpp"
 
@@ -41,6 +45,42 @@ struct ProdHeader {  // per-row product bookkeeping (16 bytes)
 };
 
 __host__ __device__ inline int64_t chunks_of(int64_t cols) { return (cols + kChunk - 1) / kChunk; }
+
+// Product saved state: [ProdHeader x rows][prefix: double x rows x nch]
+// [suffix: double x rows x nch]; prefix[r][k] is the product of the chunks
+// of row r before chunk k, suffix[r][k] of the chunks after it.
+__host__ __device__ inline double* prod_prefix(void* saved, int64_t rows) {
+  return (double*)((char*)saved + rows * (int64_t)sizeof(ProdHeader));
+}
+__host__ __device__ inline double* prod_suffix(void* saved, int64_t rows, int64_t nch) {
+  return prod_prefix(saved, rows) + rows * nch;
+}
+
+// Value of lane 63 - lane for 4- or 8-byte values (ds_bpermute per 32 bits).
+template <class A> __device__ __forceinline__ A wave_flip(A v) {
+  const int addr = (63 - (int)(threadIdx.x & 63)) << 2;
+  if constexpr (sizeof(A) == 4) {
+    return __builtin_bit_cast(A, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+  } else {
+    static_assert(sizeof(A) == 8, "4- or 8-byte values");
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(A, (uint64_t)lo | ((uint64_t)hi << 32));
+  }
+}
+
+// Exclusive prefix (lanes below) and suffix (lanes above) products over the
+// 64 lanes of a wavefront; *total gets the product of all 64.
+template <class A>
+__device__ __forceinline__ void wave_excl_products(A v, A* before, A* after, A* total) {
+  const auto mul = [](A a, A b) { return a * b; };
+  const A inc = wave_scan_incl(v, A(1), mul);
+  *before = wave_shift_up(inc, A(1));
+  *total = readlane(inc, 63);
+  const A rinc = wave_scan_incl(wave_flip(v), A(1), mul);
+  *after = wave_flip(wave_shift_up(rinc, A(1)));
+}
 
 // Order-preserving integer key of a float (-0 < +0); NaN maps to `nan_key`.
 __device__ __forceinline__ int32_t float_key(float v, int32_t nan_key) {
@@ -89,9 +129,11 @@ __device__ __forceinline__ void store_stripe(float* __restrict__ row, int64_t co
 }
 
 struct ProdAcc {  // chunk-level product state (16 bytes, combinable by DPP)
-  double p;       // product of nonzero entries (float64: see the plain kernel's traits)
-  int32_t zeros;
-  int32_t first;  // smallest zero column, INT32_MAX if none
+  double p;        // product of nonzero entries (float64: see the plain kernel's traits)
+  uint32_t zeros;  // bits 0..30: count of exact zeros; bit 31: xor of their sign bits
+                   // (a -0 counts 0x80000001, a +0 counts 1: 32-bit addition sums the
+                   // counts, below 2^31 since cols < 2^31, and xors the signs)
+  int32_t first;   // smallest zero column, INT32_MAX if none
 };
 
 }  // namespace
@@ -183,6 +225,13 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       // first occurrence is kept; once a NaN is in, the slot stops updating.
       float best[S][4];
       int32_t at[S][4];
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {  // an empty row keeps these: y = ident, column -1
+          best[u][e] = ident;
+          at[u][e] = -1;
+        }
       walk_steps<AL, NT, S>(row, 0, cols, cols, ident, t, [&](const float (&v)[S][4], int64_t c0, bool full) {
         const int64_t st = c0 / STEP;
         if (st == 0) {
@@ -241,15 +290,18 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
     } else {  // product
       const int64_t nch = chunks_of(cols);
       ProdHeader* hdr = (ProdHeader*)saved;
-      float* chunk_prod = (float*)((char*)saved + rows * (int64_t)sizeof(ProdHeader));
-      int32_t zeros = 0, first = INT32_MAX;
-      double pnz = 1.0;
+      double* __restrict__ pre = prod_prefix(saved, rows) + r * nch;
+      double* __restrict__ suf = prod_suffix(saved, rows, nch) + r * nch;
+      uint32_t zeros = 0;
+      int32_t first = INT32_MAX;
+      double pnz = 1.0;  // running product of the chunks so far
       auto comb = [](ProdAcc a, ProdAcc b) {
         return ProdAcc{a.p * b.p, a.zeros + b.zeros, a.first < b.first ? a.first : b.first};
       };
       for (int64_t k = 0; k < nch; ++k) {
         double p = 1.0;
-        int32_t z = 0, fz = INT32_MAX;
+        uint32_t z = 0;
+        int32_t fz = INT32_MAX;
         const int64_t ce = (k + 1) * kChunk < cols ? (k + 1) * kChunk : cols;
         walk_steps<AL, NT, S>(row, k * kChunk, ce, cols, 1.0f, t, [&](const float (&v)[S][4], int64_t c0, bool) {
           // A zero multiplies as 1.0 (exactly p), so the product needs no
@@ -270,24 +322,42 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 #pragma unroll
               for (int e = 0; e < 4; ++e) {
                 const bool zero = (v[u][e] == 0.0f);
-                z += zero ? 1 : 0;
+                z += zero ? (__builtin_bit_cast(uint32_t, v[u][e]) | 1u) : 0u;  // sign bit + 1
                 const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
                 fz = (zero && col < fz) ? col : fz;
               }
           }
         });
-        const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0, INT32_MAX}, comb, lds_p);
+        const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0u, INT32_MAX}, comb, lds_p);
         if (t == 0) {
-          chunk_prod[r * nch + k] = (float)tot.p;
+          pre[k] = pnz;     // chunks before k
+          suf[k] = tot.p;   // this chunk; turned into the chunks after k below
           zeros += tot.zeros;
           first = tot.first < first ? tot.first : first;
           pnz *= tot.p;
         }
-        __syncthreads();
+        __syncthreads();  // also makes suf[] visible to wavefront 0
+      }
+      // Products of the chunks after each chunk: wavefront 0 walks blocks of
+      // 64 chunks from the row's end (the barrier above ordered the stores).
+      if (t < 64) {
+        double later = 1.0;  // product of the chunks after the current block
+        for (int64_t base = ((nch - 1) >> 6) << 6; base >= 0; base -= 64) {
+          const int64_t j = base + t;
+          const double v = j < nch ? suf[j] : 1.0;
+          double below, above, all;
+          wave_excl_products(v, &below, &above, &all);
+          if (j < nch) suf[j] = above * later;
+          later *= all;
+        }
       }
       if (t == 0) {
-        hdr[r] = ProdHeader{zeros, first == INT32_MAX ? -1 : first, (float)pnz, 0.0f};
-        y[r] = zeros > 0 ? 0.0f * (float)pnz : (float)pnz;
+        const int32_t nz = (int32_t)(zeros & 0x7FFFFFFFu);
+        hdr[r] = ProdHeader{nz, first == INT32_MAX ? -1 : first, (float)pnz, 0.0f};
+        // IEEE: the product's sign is the xor of every factor's sign, zeros
+        // included; a zero times an infinity or a NaN is NaN.
+        const double zero = (zeros >> 31) ? -0.0 : 0.0;
+        y[r] = nz > 0 ? (float)(zero * pnz) : (float)pnz;
       }
     }
   }
@@ -295,110 +365,109 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 
 // ------------------------------------------------------------------ backward
 
-// Exclusive products of one zero-free row, chunk by chunk (see the file header).
-template <bool AL>
-__device__ __forceinline__ void prod_scan_row(const float* __restrict__ row, const float* __restrict__ chunk_prod,
-                              int64_t cols, float gr, float* __restrict__ out,
-                              float (&lds_tot)[kRowWaves][kPerLane / 4]) {
-  constexpr int U = kPerLane / 4;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t nch = chunks_of(cols);
-  auto mul = [](float a, float b) { return a * b; };
-  float CP = 1.0f;  // product of the chunks before this one (running)
-  for (int64_t k = 0; k < nch; ++k) {
+// Product gradient over a flat grid of (row, chunk) tiles, one work-group of
+// kProdBlock work-items per tile.  Work-item t holds kProdStripes stripes of
+// 4 consecutive columns: stripe s covers columns s * kProdBlock * 4 + 4t ..
+// + 3 of the chunk, so every load and store instruction of a wavefront is
+// one contiguous kilobyte, and the chunk is the concatenation, in column
+// order, of 64 wavefront pieces (stripe-major, then wavefront).
+//   Rows with zeros are write-only: 0 everywhere, except g * (product of the
+//   nonzero entries) at the single zero of a row with one.
+//   Zero-free rows: grad[j] = K * P<(j) * P>(j), where K = g * (product of
+//   the chunks before) * (product of the chunks after), formed in float64
+//   from the forward's saved state, and P<, P> are the exclusive products
+//   inside the chunk: inside the work-item (4 columns), over the lanes of the
+//   piece (DPP scans), and over the pieces (one wavefront scans the 64 piece
+//   products in LDS).  No division anywhere.
+constexpr int kProdBlock = 1024;
+constexpr int kProdWaves = kProdBlock / 64;
+constexpr int kProdStripes = (int)(kChunk / (kProdBlock * 4));
+static_assert(kProdStripes * kProdWaves == 64, "one wavefront scans the chunk's pieces");
+
+// Two work-groups per CU (8 wavefronts per SIMD): at most 64 VGPRs.
+template <bool AL, bool NT>
+__global__ __launch_bounds__(kProdBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g, const void* __restrict__ saved,
+                         int64_t rows, int64_t cols, int64_t nch, double inv_nch, float* __restrict__ grad) {
+  __shared__ float lds_piece[64];               // piece products, column order
+  __shared__ float lds_before[64], lds_after[64];  // exclusive products over the pieces
+  __shared__ float lds_k;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const ProdHeader* __restrict__ hdr = (const ProdHeader*)saved;
+  const double* __restrict__ pre = prod_prefix((void*)saved, rows);
+  const double* __restrict__ suf = prod_suffix((void*)saved, rows, nch);
+  const int64_t total = rows * nch;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {  // one pass unless the grid was capped
+    int64_t r = (int64_t)((double)b * inv_nch);  // b / nch, then corrected
+    if (r * nch > b) --r;
+    if ((r + 1) * nch <= b) ++r;
+    const int64_t k = b - r * nch;
     const int64_t c0 = k * kChunk;
     const bool full = c0 + kChunk <= cols;
-    // product of the chunks after this one: one load per lane, then the wavefront
-    float CS = 1.0f;
-    for (int64_t j = k + 1 + lane; j < nch; j += 64) CS *= chunk_prod[j];
-    CS = wave_reduce(CS, 1.0f, mul);
-
-    float v[U][4], m[U];
+    const ProdHeader h = hdr[r];
+    const float gr = g[r];
+    float* __restrict__ grow = grad + r * cols;
+    if (h.zeros != 0) {  // the same for the whole work-group
+      const int64_t hot = h.zeros == 1 ? h.first_zero : -1;
+      const float hot_val = gr * h.pnz;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      load_stripe<AL>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, 1.0f, v[u]);
-      m[u] = (v[u][0] * v[u][1]) * (v[u][2] * v[u][3]);  // product of this work-item's 4 columns
+      for (int s = 0; s < kProdStripes; ++s) {
+        const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
+        if (col >= cols) continue;
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = (col + e == hot) ? hot_val : 0.0f;
+        store_stripe<AL, NT>(grow, col, cols, full, o);
+      }
+      continue;
     }
-    // Across the 64 lanes: exclusive prefix (lanes below) and suffix (lanes above).
-    float E[U], F[U];
+    const float* __restrict__ xrow = x + r * cols;
+    float v[kProdStripes][4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float inc = wave_scan_incl(m[u], 1.0f, mul);
-      E[u] = wave_shift_up(inc, 1.0f);
-      const float rinc = wave_scan_incl(wave_reverse(m[u]), 1.0f, mul);
-      F[u] = wave_reverse(wave_shift_up(rinc, 1.0f));
-      if (lane == 63) lds_tot[wave][u] = inc;  // wavefront product of stripe u
+    for (int s = 0; s < kProdStripes; ++s)
+      load_stripe<AL, NT>(xrow, c0 + ((int64_t)s * kProdBlock + t) * 4, cols, full, 1.0f, v[s]);
+    float before[kProdStripes], after[kProdStripes];
+#pragma unroll
+    for (int s = 0; s < kProdStripes; ++s) {
+      const float m = (v[s][0] * v[s][1]) * (v[s][2] * v[s][3]);  // this work-item's 4 columns
+      float all;
+      wave_excl_products(m, &before[s], &after[s], &all);
+      if (lane == 0) lds_piece[s * kProdWaves + wave] = all;
     }
     __syncthreads();
-    // Across wavefronts and stripes.
-    float R[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      float before = 1.0f, after = 1.0f, all = 1.0f;
-#pragma unroll
-      for (int w2 = 0; w2 < kRowWaves; ++w2) {
-        const float q = lds_tot[w2][u];
-        if (w2 < wave) before *= q;
-        if (w2 > wave) after *= q;
-        all *= q;
-      }
-      E[u] *= before;
-      F[u] *= after;
-      R[u] = all;
+    if (wave == 0) {
+      float pb, pa, pall;
+      wave_excl_products(lds_piece[lane], &pb, &pa, &pall);
+      lds_before[lane] = pb;
+      lds_after[lane] = pa;
+      if (lane == 0) lds_k = (float)((double)gr * pre[r * nch + k] * suf[r * nch + k]);
     }
-    float SS[U];  // product of whole stripes after u
-    {
-      float acc = 1.0f;
+    __syncthreads();
+    const float K = lds_k;
 #pragma unroll
-      for (int u = U - 1; u >= 0; --u) {
-        SS[u] = acc;
-        acc *= R[u];
-      }
-    }
-    float SP = 1.0f;  // product of whole stripes before u
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const float left = gr * CP * SP * E[u];
-      const float right = F[u] * SS[u] * CS;
-      SP *= R[u];
-      const float p01 = v[u][0] * v[u][1], p23 = v[u][2] * v[u][3];
+    for (int s = 0; s < kProdStripes; ++s) {
+      const int piece = s * kProdWaves + wave;
+      const float left = (K * lds_before[piece]) * before[s];
+      const float right = after[s] * lds_after[piece];
+      const float p01 = v[s][0] * v[s][1], p23 = v[s][2] * v[s][3];
       float o[4];
-      o[0] = left * (v[u][1] * p23) * right;
-      o[1] = left * (v[u][0] * p23) * right;
-      o[2] = left * (p01 * v[u][3]) * right;
-      o[3] = left * (p01 * v[u][2]) * right;
-      store_stripe<AL>(out, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, full, o);
+      o[0] = left * (v[s][1] * p23) * right;
+      o[1] = left * (v[s][0] * p23) * right;
+      o[2] = left * (p01 * v[s][3]) * right;
+      o[3] = left * (p01 * v[s][2]) * right;
+      const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
+      if (col < cols) store_stripe<AL, NT>(grow, col, cols, full, o);
     }
-    CP *= chunk_prod[k];
-    __syncthreads();  // lds_tot is rewritten by the next chunk
+    __syncthreads();  // the LDS arrays are rewritten by the next tile
   }
 }
 
-// Product rows without zeros: grad = g * (prefix product) * (suffix
-// product), per row, persistent over rows.  Rows with zeros are written by
-// the write-only kernel below.
-template <bool AL, int S, bool NT>
-__global__ __launch_bounds__(kRowBlock) void row_bwd_kernel(const float* __restrict__ x,
-                                                            const float* __restrict__ g,
-                                                            const void* __restrict__ saved,
-                                                            int64_t rows, int64_t cols,
-                                                            float* __restrict__ grad) {
-  __shared__ float lds_tot[kRowWaves][kPerLane / 4];
-  const int64_t nch = chunks_of(cols);
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const ProdHeader h = ((const ProdHeader*)saved)[r];
-    if (h.zeros != 0) continue;
-    const float* cp = (const float*)((const char*)saved + rows * (int64_t)sizeof(ProdHeader)) + r * nch;
-    prod_scan_row<AL>(x + r * cols, cp, cols, g[r], grad + r * cols, lds_tot);
-  }
-}
-
-// Write-only gradients (sum; min/max; product rows with zeros), one tile of
-// kRowBlock x 4 columns per work-group and one 16-byte store per work-item,
-// over a flat grid of rows x tiles: for pure writes, many short work-groups
-// keep more stores in flight than a persistent loop (measured on MI355X:
-// 6.9 TB/s against 6.2 TB/s).  Product rows without zeros are skipped here;
-// the persistent kernel above scans them.
+// Write-only gradients (sum; min/max), one tile of kRowBlock x 4 columns per
+// work-group and one 16-byte store per work-item, over a flat grid of
+// rows x tiles: for pure writes, many short work-groups keep more stores in
+// flight than a persistent loop (measured on MI355X: 6.9 TB/s against
+// 6.2 TB/s).
 template <Op O, bool AL, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_fill_kernel(const float* __restrict__ g,
                                                              const void* __restrict__ saved, int64_t rows,
@@ -414,18 +483,12 @@ __global__ __launch_bounds__(kRowBlock) void row_fill_kernel(const float* __rest
     const float gr = g[r];
     int64_t hot = -1;
     float hot_val = 0.0f, fill = 0.0f;
+    static_assert(O == Op::Sum || O == Op::Max || O == Op::Min, "the product has its own kernel");
     if constexpr (O == Op::Sum) {
       fill = gr;
-    } else if constexpr (O == Op::Max || O == Op::Min) {
+    } else {
       hot = ((const int64_t*)saved)[r];
       hot_val = gr;
-    } else {
-      const ProdHeader h = ((const ProdHeader*)saved)[r];
-      if (h.zeros == 0) continue;
-      if (h.zeros == 1) {
-        hot = h.first_zero;
-        hot_val = gr * h.pnz;
-      }
     }
     float v[4];
 #pragma unroll
@@ -441,7 +504,7 @@ size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
     case RD_SUM: return 0;
     case RD_MAX:
     case RD_MIN: return (size_t)rows * 8;
-    case RD_PROD: return (size_t)rows * sizeof(ProdHeader) + (size_t)rows * chunks_of(cols) * 4;
+    case RD_PROD: return (size_t)rows * sizeof(ProdHeader) + (size_t)rows * chunks_of(cols) * 16;
     default: return 0;
   }
 }
@@ -461,14 +524,6 @@ hipError_t fwd_launch(const float* x, int64_t rows, int64_t cols, float* y, void
   return hipGetLastError();
 }
 
-template <bool AL, int S>
-hipError_t bwd_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, float* grad,
-                      int grid, bool nt, hipStream_t s) {
-  if (nt) hipLaunchKernelGGL((row_bwd_kernel<AL, S, true>), dim3(grid), dim3(kRowBlock), 0, s, x, g, saved, rows, cols, grad);
-  else hipLaunchKernelGGL((row_bwd_kernel<AL, S, false>), dim3(grid), dim3(kRowBlock), 0, s, x, g, saved, rows, cols, grad);
-  return hipGetLastError();
-}
-
 template <Op O, bool AL>
 hipError_t fwd_s(int S, const float* x, int64_t rows, int64_t cols, float* y, void* saved, int grid, bool nt,
                  hipStream_t s) {
@@ -477,18 +532,6 @@ hipError_t fwd_s(int S, const float* x, int64_t rows, int64_t cols, float* y, vo
     case 2: return fwd_launch<O, AL, 2>(x, rows, cols, y, saved, grid, nt, s);
     case 4: return fwd_launch<O, AL, 4>(x, rows, cols, y, saved, grid, nt, s);
     case 8: return fwd_launch<O, AL, 8>(x, rows, cols, y, saved, grid, nt, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <bool AL>
-hipError_t bwd_s(int S, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, float* grad,
-                 int grid, bool nt, hipStream_t s) {
-  switch (S) {
-    case 1: return bwd_launch<AL, 1>(x, g, saved, rows, cols, grad, grid, nt, s);
-    case 2: return bwd_launch<AL, 2>(x, g, saved, rows, cols, grad, grid, nt, s);
-    case 4: return bwd_launch<AL, 4>(x, g, saved, rows, cols, grad, grid, nt, s);
-    case 8: return bwd_launch<AL, 8>(x, g, saved, rows, cols, grad, grid, nt, s);
   }
   return hipErrorInvalidValue;
 }
@@ -513,18 +556,28 @@ hipError_t fill_launch(const float* g, const void* saved, int64_t rows, int64_t 
   return hipGetLastError();
 }
 
+template <bool AL>
+hipError_t prod_bwd_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
+                           float* grad, bool nt, hipStream_t s) {
+  const int64_t nch = chunks_of(cols);
+  const int64_t blocks = std::min<int64_t>(rows * nch, (int64_t)1 << 30);
+  const double inv = 1.0 / (double)nch;
+  if (nt) hipLaunchKernelGGL((row_prod_bwd_kernel<AL, true>), dim3((unsigned)blocks), dim3(kProdBlock), 0, s, x, g,
+                             saved, rows, cols, nch, inv, grad);
+  else hipLaunchKernelGGL((row_prod_bwd_kernel<AL, false>), dim3((unsigned)blocks), dim3(kProdBlock), 0, s, x, g,
+                          saved, rows, cols, nch, inv, grad);
+  return hipGetLastError();
+}
+
 template <Op O>
-hipError_t bwd_op(bool al, int S, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                  float* grad, int grid, bool nt, hipStream_t s) {
-  hipError_t e = al ? fill_launch<O, true>(g, saved, rows, cols, grad, nt, s)
-                    : fill_launch<O, false>(g, saved, rows, cols, grad, nt, s);
-  if constexpr (O != Op::Prod) {
-    return e;
+hipError_t bwd_op(bool al, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
+                  float* grad, bool nt, hipStream_t s) {
+  if constexpr (O == Op::Prod) {
+    return al ? prod_bwd_launch<true>(x, g, saved, rows, cols, grad, nt, s)
+              : prod_bwd_launch<false>(x, g, saved, rows, cols, grad, nt, s);
   } else {
-    if (e != hipSuccess) return e;
-    // product rows without zeros need their row scanned
-    return al ? bwd_s<true>(S, x, g, saved, rows, cols, grad, grid, nt, s)
-              : bwd_s<false>(S, x, g, saved, rows, cols, grad, grid, nt, s);
+    return al ? fill_launch<O, true>(g, saved, rows, cols, grad, nt, s)
+              : fill_launch<O, false>(g, saved, rows, cols, grad, nt, s);
   }
 }
 }  // namespace
@@ -544,13 +597,13 @@ hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, f
 
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, rd_op op,
                          float* grad, int cus, const Launch& l, hipStream_t s) {
+  (void)cus;  // flat grids over (row, tile): no persistent grid to size
   const bool al = (cols % 4 == 0) && ((uintptr_t)grad % 16 == 0) && (op != RD_PROD || (uintptr_t)x % 16 == 0);
-  const int grid = row_grid(rows, cus, l.grid);
   switch (op) {
-    case RD_SUM: return bwd_op<Op::Sum>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
-    case RD_MAX: return bwd_op<Op::Max>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
-    case RD_MIN: return bwd_op<Op::Min>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
-    case RD_PROD: return bwd_op<Op::Prod>(al, l.unroll, x, g, saved, rows, cols, grad, grid, l.nontemporal, s);
+    case RD_SUM: return bwd_op<Op::Sum>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
+    case RD_MAX: return bwd_op<Op::Max>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
+    case RD_MIN: return bwd_op<Op::Min>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
+    case RD_PROD: return bwd_op<Op::Prod>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -111,26 +111,29 @@ __device__ __forceinline__ void slot_put(uint64_t* slot, Item it, uint32_t tag) 
 }
 
 // Bound of a wait for published slots: a correct launch never comes
-// close, and once any wait has run out (status word set) the others stop
-// waiting too, so a broken launch still ends promptly, with the status word
-// saying so.
+// close.  A wait that runs out sets the sticky status word ctl[3] (read and
+// cleared by the host) and writes this launch's tag to ctl[4]; the other
+// waits of the same launch see the tag and stop waiting too, so a broken
+// launch still ends promptly.  The tag changes with every launch, so a
+// later launch is not cut short by an earlier one's give-up.
 constexpr int kScanSpin = 1 << 16;
 
 // Wait (in the lanes where `mine` holds) until every word of the slot at
 // src carries this launch's tag; w holds the words already loaded.
 template <int P>
 __device__ __forceinline__ void scan_wait(uint64_t (&w)[P], const uint64_t* src, bool mine, uint32_t tag,
-                                          unsigned* status) {
+                                          unsigned* ctl) {
   for (int spin = 0;; ++spin) {
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < P; ++i) ok = ok && (!mine || (uint32_t)(w[i] >> 33) == tag);
     if (ok) break;
     if (spin >= kScanSpin) {
-      __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(ctl + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctl + 4, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
-    if ((spin & 63) == 63 && __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+    if ((spin & 63) == 63 && __hip_atomic_load(ctl + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag) break;
     __builtin_amdgcn_s_sleep(1);
 #pragma unroll
     for (int i = 0; i < P; ++i)
@@ -161,9 +164,10 @@ struct ScanArgs {
   int64_t ntiles;
   uint64_t* slots;        // kScanSlots slots of kScanSlotWords words
   uint64_t* tile_first;   // segmented: per tile, tagged index of its first head
-  unsigned* ctl;          // [0] epoch, [1] next tile, [2] arrivals, [3] status
+  unsigned* ctl;          // [0] epoch, [1] next tile, [2] arrivals, [3] status, [4] give-up tag
   int exclusive;
   int aligned;            // x and out are 16-byte aligned
+  int probe;              // failure-path test: one wait for the never-published slot of tile ntiles
 };
 
 // Per tile of the segmented form: the index of the first head that falls in
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
     int64_t g = tt;
     for (int l = 0; l < kScanLevels; ++l) {
       if (l > 0 && g == 0) break;  // no earlier groups at this level or above
-      scan_wait<P>(lw, lsrc, lact && my_l == l, tag, a.ctl + 3);
+      scan_wait<P>(lw, lsrc, lact && my_l == l, tag, a.ctl);
       struct Wd { uint32_t q[P]; } wd;
 #pragma unroll
       for (int i = 0; i < P; ++i) wd.q[i] = (uint32_t)lw[i];
@@ -375,6 +379,16 @@ __global__ __launch_bounds__(1024) void scan_kernel(ScanArgs a) {
   // later tiles would wait on earlier look-backs: a chain along the array).
   // So a tile is taken only after the previous tile's prefix is known, and
   // its loads overlap the previous tile's stores.
+  if (a.probe && blockIdx.x == 0 && wave == 0) {
+    // Failure-path test: wait for the aggregate of tile ntiles, which no tile
+    // of this launch publishes (the host ensures ntiles < kScanTiles), so the
+    // wait runs out and the launch reports it.
+    const uint64_t* src = a.slots + kScanSlotWords * scan_slot(0, a.ntiles);
+    uint64_t pw[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) pw[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    scan_wait<P>(pw, src, lane == 0, tag, a.ctl);
+  }
   if (tid == 0) lds_next[0] = grab_tile(a.ctl);
   if constexpr (SEG)
     for (int i = tid; i < (int)(TE / 32); i += B) lds_heads[0][i] = 0u;
@@ -513,6 +527,7 @@ hipError_t launch_scan(const ScanCall& c, const Scratch& ws, const Launch& l, hi
   a.ctl = ws.scan_ctl;
   a.exclusive = c.exclusive ? 1 : 0;
   a.aligned = (((uintptr_t)c.x | (uintptr_t)c.out) & 15u) == 0 ? 1 : 0;
+  a.probe = (l.probe && a.ntiles < kScanTiles) ? 1 : 0;
   if (SEG && a.nheads > 0) {
     const int64_t blocks = (a.nheads + 255) / 256;
     hipLaunchKernelGGL(scan_heads_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s, c.heads, a.nheads, c.n, te,

@@ -83,8 +83,9 @@ def check_against_oracle(gpu_out: torch.Tensor, ref, x: np.ndarray, op: str, dty
         out_u = 0.0 if dtype == "float64" else 2.0 ** -24
         bound = (max(n - 1, 0) * 2.0 ** -53) * 1.001 + out_u
         ref_out = ref if dtype == "float64" else float(np.float32(ref))  # output range
-        if ref_out == 0.0 or math.isinf(ref_out):
-            assert got == ref_out, f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
+        if ref_out == 0.0 or math.isinf(ref_out) or math.isnan(ref_out):
+            # zeros and infinities compare with their sign (IEEE: the xor of the factors' signs)
+            assert same_float(got, ref_out), f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
         else:
             assert abs(got - ref) <= bound * abs(ref), f"prod/{dtype} n={n}: got {got!r}, oracle {ref!r}"
     else:

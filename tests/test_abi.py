@@ -58,6 +58,27 @@ def test_every_declared_symbol_is_exported(N):
     assert set(N.SIGNATURES) == set(decl)
 
 
+# Entry points that compute (or describe) the method: each one's comment in
+# the header names the passage of the paper that defines the operation.
+METHOD_ENTRY_POINTS = ("rd_reduce", "rd_reduce_compensated", "rd_argreduce", "rd_reduce_paper_design",
+                       "rd_segmented_reduce", "rd_scan", "rd_segmented_scan", "rd_saved_bytes",
+                       "rd_rowreduce_fwd", "rd_rowreduce_bwd", "rd_workspace_status")
+
+
+def _comment_before(name):
+    text = open(HEADER).read()
+    m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*(?:[\w\s*]+?)\b" + name + r"\s*\(", text, flags=re.S)
+    return m.group(1) if m else ""
+
+
+def test_every_method_entry_point_cites_the_paper():
+    decl = _declared_functions()
+    for name in METHOD_ENTRY_POINTS:
+        assert name in decl, name
+        comment = _comment_before(name)
+        assert re.search(r"Section \d(\.\d)?|Algorithm 1", comment), f"{name}: no citation in its header comment"
+
+
 def test_enum_values_match_header(N):
     vals = _enum_values()
     for name, v in vals.items():
@@ -121,9 +142,10 @@ def test_saved_bytes(N):
     lib = N.lib()
     assert lib.rd_saved_bytes(N.RD_SUM, 4096, 262144) == 0
     assert lib.rd_saved_bytes(N.RD_MAX, 4096, 262144) == 4096 * 8
-    # product: 16-byte row header + one float per 16384-column chunk
-    assert lib.rd_saved_bytes(N.RD_PROD, 4096, 262144) == 4096 * 16 + 4096 * 16 * 4
-    assert lib.rd_saved_bytes(N.RD_PROD, 3, 16385) == 3 * 16 + 3 * 2 * 4
+    # product: 16-byte row header + two doubles (products of the chunks before
+    # and after) per 16384-column chunk
+    assert lib.rd_saved_bytes(N.RD_PROD, 4096, 262144) == 4096 * 16 + 4096 * 16 * 16
+    assert lib.rd_saved_bytes(N.RD_PROD, 3, 16385) == 3 * 16 + 3 * 2 * 16
 
 
 def test_config_force_and_tune_table(N, tmp_path):

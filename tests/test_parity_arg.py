@@ -89,3 +89,19 @@ def test_arg_full_size():
     x = W.plain(2 ** 28, "float32", "max", config=1, salt=28)
     x[[123_456_789, 200_000_000]] = np.float32(2.0)
     check(x, "max", "float32")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("op", ["min", "max"])
+def test_arg_production_shape(op, dtype):
+    # n = 2^24 + 7 selects the launch-table row the 2^28 inputs use
+    n = 2 ** 24 + 7
+    t = {"int32": torch.int32, "uint32": torch.uint32, "int64": torch.int64, "uint64": torch.uint64,
+         "float32": torch.float32, "float64": torch.float64, "float16": torch.float16,
+         "bfloat16": torch.bfloat16}[dtype]
+    assert rd.config_get("plain", t, op, n) == rd.config_get("plain", t, op, 2 ** 28)
+    x = W.plain(n, dtype, op, config=1, salt=24)
+    rng = np.random.default_rng(24 + DTYPES.index(dtype))
+    ext_at = np.sort(rng.choice(n, size=3, replace=False))
+    x[ext_at] = x.max() if op == "max" else x.min()  # ties: the lowest index wins
+    check(x, op, dtype)

@@ -136,6 +136,59 @@ def test_coverage_all_ones_every_config():
         rd.config_force("plain", None)
 
 
+@pytest.mark.parametrize("dtype", ["int64", "float16", "bfloat16", "float64"])
+def test_coverage_all_ones_every_config_2_and_8_byte(dtype):
+    # the same coverage pin for 2- and 8-byte elements (8 and 2 per 16-byte
+    # load): a sum of ones is exact here (float16/bfloat16 accumulate in
+    # float32, exact below 2^24), so any skipped or repeated element shows
+    n = 3 * 2 ** 20 + 13
+    x = W.to_storage(np.ones(n), dtype) if dtype in ("float16", "bfloat16") else np.ones(n, W.STORAGE[dtype])
+    xg = to_gpu(x, dtype)
+    xs = to_gpu(x, dtype, pad_front=1)
+    try:
+        for block in (64, 256, 1024):
+            for unroll in (1, 2, 4, 8, 16):
+                for bpc in (1, 3, 8):
+                    for nt in (0, 1):
+                        for layout in (0, 1, 2):
+                            cfg = dict(block=block, unroll=unroll, blocks_per_cu=bpc, nontemporal=nt,
+                                       layout=layout)
+                            rd.config_force("plain", cfg)
+                            for t in (xg, xs):
+                                out = rd.reduce(t, "sum")
+                                got = bits_of(out) if dtype == "int64" else value_of(out)
+                                assert got == n, (dtype, cfg)
+    finally:
+        rd.config_force("plain", None)
+
+
+# Production launch shapes: n = 2^24 + 7 falls in the same launch-table row
+# as the benchmark's 2^28 (log2 buckets 24..62) at an eighth of the data, so
+# every (op, dtype) runs the exact kernel instantiation and grid the large
+# inputs use.
+PRODUCTION_N = 2 ** 24 + 7
+ALL_DTYPES = ["int32", "uint32", "float32", "float64", "float16", "bfloat16", "int64", "uint64"]
+
+
+@pytest.mark.parametrize("dtype", ALL_DTYPES)
+@pytest.mark.parametrize("op", OPS)
+def test_plain_production_shape(op, dtype):
+    assert rd.config_get("plain", TORCH[dtype], op, PRODUCTION_N) == rd.config_get("plain", TORCH[dtype], op, 2 ** 28)
+    if op == "prod" and dtype in INTS:
+        x = W.odd_int_supplement(PRODUCTION_N, dtype, salt=24)  # a nonzero product mod 2^k
+    else:
+        x = W.plain(PRODUCTION_N, dtype, op, config=1, salt=24)
+    _run(x, op, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float16", "bfloat16"])
+def test_compensated_production_shape(dtype):
+    t = TORCH[dtype]
+    assert rd.config_get("compensated", t, "sum", PRODUCTION_N) == rd.config_get("compensated", t, "sum", 2 ** 28)
+    x = W.plain(PRODUCTION_N, dtype, "sum", config=1, salt=24)
+    _run(x, "sum", dtype, compensated=True)
+
+
 def test_config_invariance_int_results():
     x = W.plain(2 ** 20 + 7, "int32", "xor", salt=3)
     ref = oracle.reduce(x, "xor", "int32")

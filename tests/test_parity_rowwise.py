@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import gpu_available
+from helpers import gpu_available, same_float
 from paper_1710_07358_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -42,8 +42,9 @@ def check_forward(x_np, op, y, saved):
     else:
         for r in range(x_np.shape[0]):
             ref32 = float(np.float32(yref[r]))  # the float32 output rounds once
-            if ref32 == 0.0 or math.isinf(ref32):
-                assert got[r] == ref32, (r, got[r], yref[r])
+            if ref32 == 0.0 or math.isinf(ref32) or math.isnan(ref32):
+                # a zero keeps its sign (the xor of every factor's sign)
+                assert same_float(got[r], ref32), (r, got[r], yref[r])
             else:
                 n = x_np.shape[1]
                 bound = (n - 1) * 2.0 ** -53 * 1.001 + 2.0 ** -24
@@ -131,6 +132,47 @@ def test_rowwise_signed_zero_extremes():
     x = np.array([[-0.0, 0.0, -0.0, 0.0], [0.0, -0.0, 0.0, -0.0]], np.float32)
     run_rows(x, "max")
     run_rows(x, "min")
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_rowwise_empty_rows(op):
+    # cols = 0: every row reduces to the neutral element (max/min: column -1)
+    for rows in (1, 5, 3000):
+        x = np.zeros((rows, 0), np.float32)
+        y, saved = rd.rowreduce_forward(torch.empty((rows, 0), device="cuda"), op)
+        torch.cuda.synchronize()
+        ident = {"sum": 0.0, "max": -math.inf, "min": math.inf, "prod": 1.0}[op]
+        assert np.all(y.cpu().numpy() == ident), (op, rows)
+        check_forward(x, op, y, saved)
+        grad = rd.rowreduce_backward(torch.empty((rows, 0), device="cuda"),
+                                     torch.ones(rows, device="cuda"), saved, op)
+        assert tuple(grad.shape) == (rows, 0)
+
+
+def test_rowwise_prod_signed_zeros():
+    # IEEE: the sign of a product is the xor of its factors' signs, zeros
+    # included; 0 x inf is NaN (Section 1.1's x combiner on floats)
+    rows = [[-0.0, 2.0, 3.0], [-0.0, -2.0, 1.0], [0.0, -2.0, 1.0], [-0.0, -0.0, 5.0], [0.0, -0.0, 1.0],
+            [math.inf, 0.0, 1.0], [-0.0, 1.0, 1.0], [2.0, -0.0, -1.0]]
+    x = np.array(rows, np.float32)
+    run_rows(x, "prod")
+    y, _ = rd.rowreduce_forward(torch.from_numpy(x).cuda(), "prod")
+    got = y.cpu().numpy()
+    for r, row in enumerate(rows):
+        expect = math.prod(row)
+        if math.isnan(expect):
+            assert math.isnan(got[r]), r
+        else:
+            assert got[r] == expect and math.copysign(1.0, got[r]) == math.copysign(1.0, expect), (r, got[r])
+    # the same rows spread over a long row: zeros far apart, in different chunks
+    wide = np.ones((4, 40_000), np.float32)
+    wide[0, [3, 30_000]] = [-0.0, -0.0]
+    wide[1, [17_000]] = -0.0
+    wide[1, 39_999] = -1.0
+    wide[2, [0, 16_384, 39_999]] = [-0.0, 0.0, -0.0]
+    wide[3, [20_000]] = -0.0
+    wide[3, [5]] = -3.0
+    run_rows(wide, "prod")
 
 
 def test_rowwise_prod_zero_counts():

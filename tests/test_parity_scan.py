@@ -7,7 +7,9 @@ accumulator) + V (the lane's running fold) = 2V + U + 24 roundings, each
 bounded by u times the running sum of |x| (u = 2^-24 for float32, float16 and
 bfloat16 data, which accumulate in float32; 2^-53 for float64).  With V <= 8
 and U <= 8 that is at most 48, so |out - exact| <= 48 u sum|x| over the prefix
-(tile prefixes travel in float64 and add far less).  Products accumulate in float64:
+(tile prefixes travel in float64 and add far less).  The tests hold float32,
+float16 and bfloat16 sums to the float-sum bar 2^-20 sum|x| (tighter than
+48 u = 2^-18.4), float64 sums to 48 u.  Products accumulate in float64:
 any product tree of k factors is within (k-1) 2^-53 of the exact product,
 plus one float32 rounding of the output.
 """
@@ -57,9 +59,12 @@ def check_scan(x_np, op, dtype, out, exclusive, heads=None):
     if op == "sum":
         u = 2.0 ** -53 if dtype == "float64" else 2.0 ** -24
         scale = oracle.scan(abs_storage(x_np, dtype), "sum", dtype, exclusive=exclusive, heads=heads)
+        # the float-sum bar (2^-20 sum|x| over the prefix), or the kernel's
+        # own worst-case bound 48u sum|x| where that is tighter (float64)
+        tol = min(2.0 ** -20, 48 * u)
         err = np.abs(got - ref)
-        bad = np.nonzero(err > 48 * u * scale)[0]
-        assert bad.size == 0, f"sum/{dtype}: {bad.size} beyond 48u sum|x|, first at {bad[:5]}: " \
+        bad = np.nonzero(err > tol * scale)[0]
+        assert bad.size == 0, f"sum/{dtype}: {bad.size} beyond {tol:.3g} sum|x|, first at {bad[:5]}: " \
                               f"got {got[bad[:5]]}, exact {ref[bad[:5]]}"
         return
     # products: k factors in the prefix (position inside the run)
@@ -73,7 +78,14 @@ def check_scan(x_np, op, dtype, out, exclusive, heads=None):
     k = np.arange(n) - start + (0 if exclusive else 1)
     out_u = 0.0 if dtype == "float64" else 2.0 ** -24
     bound = np.maximum(k - 1, 0) * 2.0 ** -53 * 1.001 + out_u
-    assert np.all(np.abs(got - ref) <= bound * np.abs(ref)), f"prod/{dtype}"
+    ref_out = ref if dtype == "float64" else ref.astype(np.float32).astype(np.float64)
+    special = (ref_out == 0) | np.isinf(ref_out) | np.isnan(ref_out)
+    # zeros and infinities carry the xor of the factors' signs; NaN stays NaN
+    same = (np.isnan(got) & np.isnan(ref_out)) | ((got == ref_out) & (np.signbit(got) == np.signbit(ref_out)))
+    bad = np.nonzero(special & ~same)[0]
+    assert bad.size == 0, f"prod/{dtype}: {bad.size} zero/inf/NaN results differ, first at {bad[:5]}"
+    ok = np.abs(got - ref) <= bound * np.abs(ref)
+    assert np.all(ok | special), f"prod/{dtype}"
 
 
 def run_scan(x_np, op, dtype, exclusive, heads=None, pad=0, inplace=False):
@@ -245,4 +257,4 @@ def test_scan_full_size_int32_and_sampled_float32():
     for i in (4095, 4096 * 64 + 5, (1 << 27) + 12_345, n - 1):
         ref, asum = oracle.exact_sum(xf_np[: i + 1], "float32")
         got_i = float(out[i].item())
-        assert abs(got_i - ref) <= 48 * 2.0 ** -24 * asum, (i, got_i, ref)
+        assert abs(got_i - ref) <= 2.0 ** -20 * asum, (i, got_i, ref)
