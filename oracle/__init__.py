@@ -14,7 +14,9 @@ It wraps ``oracle.c`` (plain C, built with gcc, no fast-math) through ctypes:
   lowest attaining index;
 * segmented and row-wise forms, and row-wise gradients;
 * scans (the prefix form of the reduction), plain or restarted at segment
-  heads.
+  heads;
+* a timing baseline (not a correctness source): Algorithm 1's float32 left
+  fold accumulated in double, on one thread or over several threads.
 
 Arrays are numpy arrays on the host.  bfloat16 data travels as ``uint16``
 bit patterns with ``dtype="bfloat16"``; float16 may be ``np.float16`` or
@@ -50,7 +52,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               "-fno-fast-math", "-ffp-contract=off",
+                               "-fno-fast-math", "-ffp-contract=off", "-pthread",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -78,9 +80,10 @@ def _load():
         lib.orc_scan.argtypes = [vp, i64, ci, ci, ci, vp, i64, vp]
         lib.orc_row_forward.argtypes = [vp, i64, i64, ci, vp, vp, vp]
         lib.orc_row_grad.argtypes = [vp, i64, i64, ci, vp, vp]
+        lib.orc_fold_sum_f32.argtypes = [vp, i64, ci, dp]
         for f in (lib.orc_fold_u32, lib.orc_fold_u64, lib.orc_fold_u16, lib.orc_argext_int, lib.orc_exact_sum,
                   lib.orc_prod, lib.orc_minmax, lib.orc_segmented, lib.orc_scan, lib.orc_row_forward,
-                  lib.orc_row_grad):
+                  lib.orc_row_grad, lib.orc_fold_sum_f32):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -231,3 +234,13 @@ def row_grad(x: np.ndarray, op: str, g: np.ndarray) -> np.ndarray:
     grad = np.empty((rows, cols), np.float64)
     _check(_load().orc_row_grad(_ptr(x), rows, cols, OPS[op], _ptr(g), _ptr(grad)), "row_grad")
     return grad
+
+
+def fold_sum_f32(x: np.ndarray, threads: int = 1) -> float:
+    """Algorithm 1's left fold of a float32 array in double: the CPU timing
+    baseline.  With threads > 1, contiguous chunks fold on their own threads
+    and the partial sums add in chunk order."""
+    x = _storage(np.ravel(x), "float32")
+    d = ctypes.c_double()
+    _check(_load().orc_fold_sum_f32(_ptr(x), x.size, int(threads), ctypes.byref(d)), "fold_sum_f32")
+    return d.value

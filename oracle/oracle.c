@@ -16,17 +16,20 @@
  *     long accumulator (units of 2^-1074), rounded once to double;
  *   - float product: a left fold in double-double arithmetic;
  *   - row-wise gradients: their definitions, with exclusive prefix/suffix
- *     products in double-double.
+ *     products in double-double;
+ *   - a timing baseline only: Algorithm 1's float32 left fold in double, on
+ *     one thread or split into contiguous chunks over several threads.
  *
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
  * load this file.  It shares nothing with the GPU path.
  *
- * Build: gcc -O2 -fPIC -shared (no -ffast-math: the float code relies on
+ * Build: gcc -O2 -fPIC -shared -pthread (no -ffast-math: the float code relies on
  * strict IEEE evaluation and on fma being exact-then-rounded).
  */
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -649,5 +652,56 @@ int orc_row_grad(const float* x, int64_t rows, int64_t cols, int op, const doubl
             }
         } else return -1;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 as a CPU timing baseline (not a correctness source).     */
+/* ------------------------------------------------------------------ */
+
+/* One thread's share: the left fold of Algorithm 1 over x[lo..hi) of a
+   float32 array, accumulated in double (Section 1.1's footnote names double
+   precision as the simple remedy for float rounding). */
+typedef struct {
+    const float* x;
+    int64_t lo, hi;
+    double s;
+} fold_part;
+
+static void* fold_part_run(void* arg) {
+    fold_part* p = (fold_part*)arg;
+    double s = 0.0;
+    for (int64_t i = p->lo; i < p->hi; ++i) s = s + (double)p->x[i];
+    p->s = s;
+    return 0;
+}
+
+int orc_fold_sum_f32(const float* x, int64_t n, int threads, double* out) {
+    enum { MAX_THREADS = 256 };
+    if (n < 0 || threads < 1 || threads > MAX_THREADS) return -2;
+    fold_part part[MAX_THREADS];
+    pthread_t tid[MAX_THREADS];
+    for (int t = 0; t < threads; ++t) {
+        part[t].x = x;
+        part[t].lo = n / threads * t + (t < n % threads ? t : n % threads);
+        part[t].hi = part[t].lo + n / threads + (t < n % threads ? 1 : 0);
+        part[t].s = 0.0;
+    }
+    if (threads == 1) {
+        fold_part_run(&part[0]);
+        *out = part[0].s;
+        return 0;
+    }
+    int started = 0;
+    for (int t = 1; t < threads; ++t) {
+        if (pthread_create(&tid[t], 0, fold_part_run, &part[t]) != 0) break;
+        ++started;
+    }
+    fold_part_run(&part[0]);
+    for (int t = 1; t <= started; ++t) pthread_join(tid[t], 0);
+    if (started != threads - 1) return -4;
+    double s = 0.0; /* the chunks' partial sums, folded in chunk order */
+    for (int t = 0; t < threads; ++t) s = s + part[t].s;
+    *out = s;
     return 0;
 }

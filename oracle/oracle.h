@@ -98,6 +98,15 @@ int orc_row_forward(const float* x, int64_t rows, int64_t cols, int op, double* 
 int orc_row_grad(const float* x, int64_t rows, int64_t cols, int op, const double* g,
                  double* grad);
 
+/* Timing baseline, not a correctness source: Algorithm 1 (Summation) as a
+ * left fold of a float32 array accumulated in double.  threads = 1 folds
+ * x[0..n) in index order on the calling thread; threads = T > 1 splits x into
+ * T contiguous chunks of near-equal size, folds each on its own thread and
+ * adds the T partial sums in chunk order (a fixed order, so the result is
+ * reproducible for a given T).  1 <= T <= 256; returns -4 if a thread cannot
+ * be started. */
+int orc_fold_sum_f32(const float* x, int64_t n, int threads, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -709,3 +709,33 @@ def test_scan_segments_end_values_match_segment_reduction():
 def test_scan_rejects_decreasing_heads():
     with pytest.raises(ValueError):
         oracle.scan(np.ones(10, np.int32), "sum", "int32", heads=np.array([5, 2]))
+
+
+# ------------------------------------------------- timing baseline (Algorithm 1)
+
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 1023, 100_003])
+def test_fold_sum_f32_closed_form(n, threads):
+    # integers 0..n-1 held exactly in float32 and in the double accumulator:
+    # every split gives n(n-1)/2 exactly, also with more threads than elements
+    x = np.arange(n, dtype=np.float32)
+    assert oracle.fold_sum_f32(x, threads) == n * (n - 1) // 2
+
+
+@pytest.mark.parametrize("threads", [1, 5])
+def test_fold_sum_f32_within_double_fold_bound(threads):
+    # a left fold in double over n values is within (n - 1) 2^-53 sum|x| of the
+    # exact sum (math.fsum is correctly rounded); the chunked fold adds T - 1
+    # more additions, within the same bound
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, 200_001).astype(np.float32)
+    exact = math.fsum(x.astype(np.float64))
+    bound = (x.size + threads) * 2.0 ** -53 * float(np.abs(x.astype(np.float64)).sum())
+    assert abs(oracle.fold_sum_f32(x, threads) - exact) <= bound
+
+
+def test_fold_sum_f32_rejects_bad_thread_counts():
+    with pytest.raises(ValueError):
+        oracle.fold_sum_f32(np.ones(4, np.float32), 0)
+    with pytest.raises(ValueError):
+        oracle.fold_sum_f32(np.ones(4, np.float32), 257)
