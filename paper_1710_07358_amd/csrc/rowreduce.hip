@@ -10,14 +10,17 @@
 //     chunk where it was first reached, and ties resolve to the smaller
 //     column when lanes, wavefronts and slots are combined.
 //   product also records, per row, the number of exact zeros, the first
-//     zero's column and the product of the nonzero entries, and per chunk
+//     zero's column, the product of the nonzero entries and where its
+//     infinite or NaN entries are (none, one column, several), and per chunk
 //     of kChunk columns the products of all chunks before it and of all
 //     chunks after it, in float64 (the state the gradient needs).
 // Backward (grad = dy/dx * g):
 //   sum     -> g[r] broadcast (write-only);
 //   max/min -> g[r] at the saved column, 0 elsewhere (write-only);
 //   product -> rows with >= 2 zeros: 0; one zero: g*prod(nonzeros) at the
-//              zero; no zero: g * prod_{i<j} x * prod_{i>j} x.  One
+//              zero, 0 elsewhere (IEEE NaN where the other entries pair a
+//              zero with an infinity or NaN); no zero:
+//              g * prod_{i<j} x * prod_{i>j} x.  One
 //              work-group per (row, chunk) over a flat grid: the chunk's own
 //              exclusive prefix and suffix products come from DPP scans over
 //              the lanes and one scan over the chunk's 64 wavefront pieces,
@@ -41,7 +44,7 @@ struct ProdHeader {  // per-row product bookkeeping (16 bytes)
   int32_t zeros;
   int32_t first_zero;  // column of the first exact zero, -1 if none
   float pnz;           // product of the nonzero entries
-  float reserved;
+  int32_t nonfinite;   // infinite or NaN entries: -1 none, -2 two or more, else the only one's column
 };
 
 __host__ __device__ inline int64_t chunks_of(int64_t cols) { return (cols + kChunk - 1) / kChunk; }
@@ -150,30 +153,31 @@ template <int S> constexpr int64_t row_step() { return (int64_t)kRowBlock * 4 * 
 // Whole steps are software-pipelined -- the next step's loads are issued
 // before the current one is folded -- and use unguarded loads; only a ragged
 // last step takes the guarded path, filling missing columns with `fill`.
+// The prefetch inside the loop is unconditional (the last whole step is
+// peeled), so the compiler's wait before the fold covers the current step's
+// loads only, not the ones just issued.
 template <bool AL, bool NT, int S, class Body>
 __device__ __forceinline__ void walk_steps(const float* __restrict__ row, int64_t cb, int64_t ce, int64_t cols,
                                            float fill, int t, Body body) {
   constexpr int64_t STEP = row_step<S>();
   int64_t c0 = cb;
   if (c0 + STEP <= ce) {
-    float cur[S][4], nxt[S][4];
+    float cur[S][4];
 #pragma unroll
     for (int u = 0; u < S; ++u) load_stripe<AL, NT>(row, c0 + ((int64_t)u * kRowBlock + t) * 4, cols, true, fill, cur[u]);
-    for (; c0 + STEP <= ce; c0 += STEP) {
-      const bool more = c0 + 2 * STEP <= ce;
-      if (more) {
+    for (; c0 + 2 * STEP <= ce; c0 += STEP) {
+      float nxt[S][4];
 #pragma unroll
-        for (int u = 0; u < S; ++u)
-          load_stripe<AL, NT>(row, c0 + STEP + ((int64_t)u * kRowBlock + t) * 4, cols, true, fill, nxt[u]);
-      }
+      for (int u = 0; u < S; ++u)
+        load_stripe<AL, NT>(row, c0 + STEP + ((int64_t)u * kRowBlock + t) * 4, cols, true, fill, nxt[u]);
       body(cur, c0, true);
-      if (more) {
 #pragma unroll
-        for (int u = 0; u < S; ++u)
+      for (int u = 0; u < S; ++u)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) cur[u][e] = nxt[u][e];
-      }
+        for (int e = 0; e < 4; ++e) cur[u][e] = nxt[u][e];
     }
+    body(cur, c0, true);
+    c0 += STEP;
   }
   if (c0 < ce) {
     float v[S][4];
@@ -193,8 +197,24 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
   __shared__ float lds_f[kRowWaves];
   __shared__ uint64_t lds_u[kRowWaves];
   __shared__ ProdAcc lds_p[kRowWaves];
+  // Product rows: count of infinite or NaN entries and the first one's
+  // column, one pair per row parity.  Work-item 0 reads and re-arms a row's
+  // pair after the row's last barrier; the other wavefronts may already be on
+  // the next row, which uses the other pair, and cannot reach the row after it
+  // before passing a barrier of the next row, which work-item 0 reaches only
+  // after the re-arm.
+  __shared__ unsigned lds_nf[2];
+  __shared__ int32_t lds_nf_col[2];
+  if constexpr (O == Op::Prod) {
+    if (t < 2) {
+      lds_nf[t] = 0u;
+      lds_nf_col[t] = INT32_MAX;
+    }
+    __syncthreads();
+  }
+  int parity = 0;
 
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x, parity ^= 1) {
     const float* __restrict__ row = x + r * cols;
     if constexpr (O == Op::Sum) {
       float acc[S][4];
@@ -304,29 +324,35 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
         int32_t fz = INT32_MAX;
         const int64_t ce = (k + 1) * kChunk < cols ? (k + 1) * kChunk : cols;
         walk_steps<AL, NT, S>(row, k * kChunk, ce, cols, 1.0f, t, [&](const float (&v)[S][4], int64_t c0, bool) {
-          // A zero multiplies as 1.0 (exactly p), so the product needs no
-          // 64-bit select; zeros are counted, and the first located, only in
-          // the steps where some lane of the wavefront holds one.
-          bool anyz = false;
+          // Fast path: multiply the step in, unguarded.  A zero factor always
+          // leaves +-0 or NaN, so while every lane's product stays a normal
+          // number the step held no zero and q is exactly what the zero-aware
+          // walk below would give.  Otherwise (a zero, or an infinity, NaN,
+          // overflow or underflow in some lane) the wavefront redoes the step
+          // from p: zeros multiply as 1.0 and are counted, the first located.
+          double q = p;
+#pragma unroll
+          for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q *= (double)v[u][e];
+          if (__builtin_amdgcn_ballot_w64(!__builtin_isnormal(q)) == 0ull) {
+            p = q;
+            return;
+          }
 #pragma unroll
           for (int u = 0; u < S; ++u)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const bool zero = (v[u][e] == 0.0f);
-              anyz = anyz || zero;
               p *= (double)(zero ? 1.0f : v[u][e]);
-            }
-          if (__builtin_amdgcn_ballot_w64(anyz) != 0ull) {
-#pragma unroll
-            for (int u = 0; u < S; ++u)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const bool zero = (v[u][e] == 0.0f);
-                z += zero ? (__builtin_bit_cast(uint32_t, v[u][e]) | 1u) : 0u;  // sign bit + 1
-                const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
-                fz = (zero && col < fz) ? col : fz;
+              z += zero ? (__builtin_bit_cast(uint32_t, v[u][e]) | 1u) : 0u;  // sign bit + 1
+              const int32_t col = (int32_t)(c0 + ((int64_t)u * kRowBlock + t) * 4 + e);
+              fz = (zero && col < fz) ? col : fz;
+              if (!__builtin_isfinite(v[u][e])) {  // filled columns of a ragged step hold 1.0
+                atomicAdd(&lds_nf[parity], 1u);
+                atomicMin(&lds_nf_col[parity], col);
               }
-          }
+            }
         });
         const ProdAcc tot = block_reduce(ProdAcc{p, z, fz}, ProdAcc{1.0, 0u, INT32_MAX}, comb, lds_p);
         if (t == 0) {
@@ -353,7 +379,12 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
       }
       if (t == 0) {
         const int32_t nz = (int32_t)(zeros & 0x7FFFFFFFu);
-        hdr[r] = ProdHeader{nz, first == INT32_MAX ? -1 : first, (float)pnz, 0.0f};
+        const unsigned nf = lds_nf[parity];
+        const int32_t nf_col = lds_nf_col[parity];
+        lds_nf[parity] = 0u;
+        lds_nf_col[parity] = INT32_MAX;
+        hdr[r] = ProdHeader{nz, first == INT32_MAX ? -1 : first, (float)pnz,
+                            nf == 0u ? -1 : (nf == 1u ? nf_col : -2)};
         // IEEE: the product's sign is the xor of every factor's sign, zeros
         // included; a zero times an infinity or a NaN is NaN.
         const double zero = (zeros >> 31) ? -0.0 : 0.0;
@@ -371,8 +402,11 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 // + 3 of the chunk, so every load and store instruction of a wavefront is
 // one contiguous kilobyte, and the chunk is the concatenation, in column
 // order, of 64 wavefront pieces (stripe-major, then wavefront).
-//   Rows with zeros are write-only: 0 everywhere, except g * (product of the
-//   nonzero entries) at the single zero of a row with one.
+//   Rows with zeros are write-only: g * (product of the nonzero entries) at
+//   the single zero of a row with one; every other column's product of the
+//   other entries holds a zero, so it is g * 0 -- or NaN (IEEE 0 * inf) when
+//   those other entries hold an infinity or a NaN, which the forward's count
+//   of non-finite entries tells.
 //   Zero-free rows: grad[j] = K * P<(j) * P>(j), where K = g * (product of
 //   the chunks before) * (product of the chunks after), formed in float64
 //   from the forward's saved state, and P<, P> are the exclusive products
@@ -411,13 +445,17 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
     if (h.zeros != 0) {  // the same for the whole work-group
       const int64_t hot = h.zeros == 1 ? h.first_zero : -1;
       const float hot_val = gr * h.pnz;
+      const float zero_val = gr * 0.0f;
 #pragma unroll
       for (int s = 0; s < kProdStripes; ++s) {
         const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
         if (col >= cols) continue;
         float o[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) o[e] = (col + e == hot) ? hot_val : 0.0f;
+        for (int e = 0; e < 4; ++e) {
+          const bool nan_here = h.nonfinite == -2 || (h.nonfinite >= 0 && col + e != h.nonfinite);
+          o[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : zero_val);
+        }
         store_stripe<AL, NT>(grow, col, cols, full, o);
       }
       continue;

@@ -22,8 +22,18 @@ SHAPES = [(1, 1), (3, 5), (7, 4099), (2, 16384), (5, 16385), (4, 40_000), (3, 65
 
 
 def prod_grad_ok(got, ref):
-    scale = np.max(np.abs(ref), axis=1, keepdims=True)
-    return np.all(np.abs(got - ref) <= 2.0 ** -12 * np.abs(ref) + 2.0 ** -40 * scale)
+    # NaN and infinite entries (IEEE products of the other entries, e.g.
+    # 0 x inf) must match exactly; finite ones within 2^-12 |ref| plus a floor
+    # relative to the row's largest finite gradient
+    nan_r, inf_r = np.isnan(ref), np.isinf(ref)
+    if not (np.array_equal(np.isnan(got), nan_r) and np.array_equal(np.isinf(got), inf_r)
+            and np.array_equal(got[inf_r], ref[inf_r])):
+        return False
+    fin = ~(nan_r | inf_r)
+    r = np.where(fin, ref, 0.0)
+    g = np.where(fin, got, 0.0)
+    scale = np.max(np.abs(r), axis=1, keepdims=True)
+    return bool(np.all(np.abs(g - r) <= 2.0 ** -12 * np.abs(r) + 2.0 ** -40 * scale))
 
 
 def check_forward(x_np, op, y, saved):
