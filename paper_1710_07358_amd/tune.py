@@ -71,13 +71,17 @@ def _valid(kind: str, cfg: dict) -> bool:
     return cfg["block"] * cfg["blocks_per_cu"] <= 4096
 
 
-def descend(kind: str, start: dict, run, passes: int = 2, log=None) -> tuple[dict, float]:
-    """Coordinate descent over SPACE[kind] from `start`; run() times the forced call."""
+def descend(kind: str, start: dict, run, passes: int = 2, log=None, space: dict | None = None,
+            timer=None) -> tuple[dict, float]:
+    """Coordinate descent over `space` (default SPACE[kind]) from `start`;
+    timer(run) (default time_call) times the forced call."""
+    space = SPACE[kind] if space is None else space
+    timer = time_call if timer is None else timer
     best = dict(start)
     rd.config_force(kind, best)
-    best_t = time_call(run)
+    best_t = timer(run)
     for _ in range(passes):
-        for key, values in SPACE[kind].items():
+        for key, values in space.items():
             for v in values:
                 if v == best[key]:
                     continue
@@ -85,7 +89,7 @@ def descend(kind: str, start: dict, run, passes: int = 2, log=None) -> tuple[dic
                 if not _valid(kind, cand):
                     continue
                 rd.config_force(kind, cand)
-                t = time_call(run)
+                t = timer(run)
                 if log:
                     log(f"  {kind} {cand} {t * 1e6:.1f} us")
                 if t < best_t:
@@ -144,9 +148,18 @@ def _case_runner(kind: str, esize: int, opclass: int, n: int, dev):
     raise ValueError(kind)
 
 
+TABLE_HEADER = "# kind esize opclass log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout"
+
+
+def table_line(kind: str, esize: int, opclass: int, lo: int, hi: int, cfg: dict) -> str:
+    """One entry of the launch table in the format rd_tune_load reads."""
+    return (f"{KIND_ID[kind]} {esize} {opclass} {lo} {hi} {cfg['block']} {cfg['unroll']} "
+            f"{cfg['blocks_per_cu']} {cfg['nontemporal']} {cfg['layout']}")
+
+
 def tune_table(kinds, esizes, log) -> list[str]:
     dev = torch.device("cuda", torch.cuda.current_device())
-    lines = ["# kind esize opclass log2n_lo log2n_hi block unroll blocks_per_cu nontemporal layout"]
+    lines = [TABLE_HEADER]
     for kind in kinds:
         row_kind = kind in ("rowwise", "rowwise_bwd")
         for esize in esizes:
@@ -171,8 +184,7 @@ def tune_table(kinds, esizes, log) -> list[str]:
                     best, t = descend(kind, start, run)
                     log(f"{kind} esize={esize} opclass={opclass} n=2^{n.bit_length() - 1}: {best} "
                         f"{t * 1e6:.1f} us {nbytes / t / 1e9:.0f} GB/s")
-                    lines.append(f"{KIND_ID[kind]} {esize} {opclass} {lo} {hi} {best['block']} {best['unroll']} "
-                                 f"{best['blocks_per_cu']} {best['nontemporal']} {best['layout']}")
+                    lines.append(table_line(kind, esize, opclass, lo, hi, best))
                     del run
                     torch.cuda.empty_cache()
     return lines
