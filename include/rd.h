@@ -38,9 +38,16 @@
 
 #ifdef __cplusplus
 extern "C" {
+/* C++ sees the enums with int as their fixed underlying type, so every int a
+ * C caller passes (valid or not) is a value of the enum type and the
+ * library's range checks read it without undefined behaviour; the layout is
+ * the C enum's (an int). */
+#define RD_ENUM_INT : int
+#else
+#define RD_ENUM_INT
 #endif
 
-typedef enum rd_dtype {
+typedef enum rd_dtype RD_ENUM_INT {
     RD_I32 = 0,  /* int32 */
     RD_U32 = 1,  /* uint32 */
     RD_F32 = 2,  /* IEEE binary32 */
@@ -51,11 +58,11 @@ typedef enum rd_dtype {
     RD_U64 = 7   /* uint64 */
 } rd_dtype;
 
-typedef enum rd_op {
+typedef enum rd_op RD_ENUM_INT {
     RD_SUM = 0, RD_PROD = 1, RD_MIN = 2, RD_MAX = 3, RD_AND = 4, RD_OR = 5, RD_XOR = 6
 } rd_op;
 
-typedef enum rd_status {
+typedef enum rd_status RD_ENUM_INT {
     RD_OK = 0,
     RD_ERR_INVALID_ARG = -1, /* null pointer, negative size, misaligned pointer, bad enum */
     RD_ERR_UNSUPPORTED = -2, /* (dtype, op) pair the entry point does not offer */
@@ -95,7 +102,7 @@ typedef struct rd_config {
  * block x unroll x 16 bytes of input, with unroll 4 or 8 (8 when 8 or more
  * is given, else 4); `blocks_per_cu` sizes the persistent grid,
  * `nontemporal` applies to loads and stores, and `layout` is ignored. */
-typedef enum rd_kind {
+typedef enum rd_kind RD_ENUM_INT {
     RD_KIND_PLAIN = 0, RD_KIND_COMPENSATED = 1, RD_KIND_SEGMENTED = 2, RD_KIND_ROWWISE = 3,
     RD_KIND_ROWWISE_BWD = 4, RD_KIND_SCAN = 5, RD_KIND_SEGMENTED_SCAN = 6
 } rd_kind;
@@ -115,7 +122,7 @@ rd_status rd_workspace_destroy(rd_workspace* ws);
 rd_status rd_workspace_reset(rd_workspace* ws, void* stream);
 
 /* Bits of rd_workspace_status. */
-typedef enum rd_wait_flags {
+typedef enum rd_wait_flags RD_ENUM_INT {
     RD_WAIT_GRID = 1, /* a grid-stage wait of rd_reduce, rd_reduce_compensated, rd_argreduce or a
                          segment-carry wait of rd_segmented_reduce ran out */
     RD_WAIT_SCAN = 2  /* a look-back wait of rd_scan / rd_segmented_scan ran out */
