@@ -109,8 +109,9 @@ typedef enum rd_kind RD_ENUM_INT {
 
 /* ---- library and workspace management ---------------------------------- */
 
-/* Query the current device (compute-unit count, architecture).  Called
- * implicitly by every entry point; returns RD_ERR_HIP without a device. */
+/* Query the current device (compute-unit count, architecture) and look up
+ * the device address of its rd_reduce_noalloc array.  Called implicitly by
+ * every entry point; returns RD_ERR_HIP without a device. */
 rd_status rd_init(void);
 
 /* Create a workspace on the given device (allocates device memory; must not
@@ -136,7 +137,7 @@ typedef enum rd_wait_flags RD_ENUM_INT {
  * status word in the workspace; the launch then ends normally but its result
  * is unspecified.
  *   ws    : one workspace, or NULL for every workspace (default and explicit)
- *           of the current device
+ *           of the current device and the device's rd_reduce_noalloc array
  *   flags : out; rd_wait_flags bits of the words found set
  * Synchronises the device (so it must not be called during graph capture),
  * reads the words and clears them.  Returns RD_ERR_WORKSPACE if ws belongs to
@@ -144,7 +145,7 @@ typedef enum rd_wait_flags RD_ENUM_INT {
 rd_status rd_workspace_status(rd_workspace* ws, unsigned* flags);
 
 /* Test hook for the failure path of the bounded waits.  While `on` is
- * nonzero, every rd_reduce and rd_scan launch adds one wait for a slot that
+ * nonzero, every rd_reduce, rd_reduce_noalloc and rd_scan launch adds one wait for a slot that
  * nothing publishes: the wait runs out (after its bound; about a second for
  * rd_reduce), rd_workspace_status then reports it, and the kernel still ends
  * normally (with an unspecified result).  Not for production use. */
@@ -172,6 +173,27 @@ rd_status rd_out_dtype(rd_dtype dt, rd_op op, rd_dtype* out);
  * per-work-group partials in index order and writes out. */
 rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
                     rd_workspace* ws, void* stream);
+
+/* rd_reduce for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels, launch table and result as rd_reduce (bitwise identical for
+ * the same input), but no workspace -- the grid stage's counter, status word
+ * and partials live in a fixed array of 128 KiB + 256 bytes that the library
+ * holds on every GPU it runs on until the process ends.  The call allocates
+ * nothing and does not synchronise; it enqueues one small kernel that re-arms
+ * the array (zeroes the counter and the partial slots it will use; a kernel,
+ * not a memset, so it can be captured) and then the reduction.
+ *   x, n, dt, op, out, stream : as for rd_reduce
+ * The persistent grid is capped at the array's 4096 work-group slots; the
+ * kernel loops over any n, so no input size is rejected.  The device address
+ * of the array is looked up once per device (in rd_init, or on the first call
+ * on that device).  Every call on one GPU shares its array: calls that may
+ * overlap on one GPU (different streams, or host threads) race and give
+ * unspecified results.  A bounded wait that runs out sets the array's status
+ * word, which rd_workspace_status(NULL, ...) reports (RD_WAIT_GRID) and
+ * clears. */
+rd_status rd_reduce_noalloc(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out,
+                            void* stream);
 
 /* Compensated sum (the Kahan-style remedy the footnotes of Section 1.1
  * mention): every work-item keeps error-free two-sum (value, error) pairs in

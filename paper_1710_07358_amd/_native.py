@@ -46,6 +46,7 @@ SIGNATURES = {
     "rd_dtype_size": (_sz, [_ci]),
     "rd_out_dtype": (_ci, [_ci, _ci, ctypes.POINTER(_ci)]),
     "rd_reduce": (_ci, [_vp, _i64, _ci, _ci, _vp, _vp, _vp]),
+    "rd_reduce_noalloc": (_ci, [_vp, _i64, _ci, _ci, _vp, _vp]),
     "rd_reduce_compensated": (_ci, [_vp, _i64, _ci, _vp, _vp, _vp]),
     "rd_segmented_reduce": (_ci, [_vp, _vp, _i64, _ci, _ci, _vp, _vp, _vp]),
     "rd_reduce_paper_design": (_ci, [_vp, _i64, _ci, _ci, _ci, _vp, _vp, _vp]),

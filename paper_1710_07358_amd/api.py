@@ -125,6 +125,26 @@ def reduce(x: torch.Tensor, op: str, out: torch.Tensor | None = None, workspace:
     return out
 
 
+def reduce_noalloc(x: torch.Tensor, op: str, out: torch.Tensor | None = None, n: int | None = None) -> torch.Tensor:
+    """reduce() without a workspace: the library's fixed per-GPU scratch array
+    carries the grid stage, and the call allocates no device memory (pass
+    `out` as well to keep the whole call allocation-free).  Calls that may
+    overlap on one GPU race."""
+    x = _dev_tensor(x, "x")
+    count = x.numel() if n is None else int(n)
+    if count > x.numel():
+        raise ValueError("n exceeds x.numel()")
+    odt = out_dtype(x.dtype, op)
+    if out is None:
+        out = torch.empty((), dtype=odt, device=x.device)
+    elif out.dtype != odt or not out.is_cuda:
+        raise ValueError(f"out must be a {odt} tensor on the GPU")
+    with torch.cuda.device(x.device):
+        N.check(N.lib().rd_reduce_noalloc(x.data_ptr() if count else None, count, _dt(x), _op(op),
+                                          out.data_ptr(), _stream(x.device)))
+    return out
+
+
 def reduce_compensated(x: torch.Tensor, out: torch.Tensor | None = None,
                        workspace: Workspace | None = None) -> torch.Tensor:
     """Compensated (two-sum) sum of float32/float16/bfloat16 data, float64 result."""

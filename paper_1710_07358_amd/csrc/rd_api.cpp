@@ -30,15 +30,14 @@ struct rd_workspace {
 
 namespace {
 
-thread_local std::string g_last_error;
+// A fixed buffer, so that reporting an error never allocates.
+thread_local char g_last_error[512];
 
 rd_status fail(rd_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  std::vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
   va_end(ap);
-  g_last_error = buf;
   return st;
 }
 
@@ -145,6 +144,64 @@ rd_status create_workspace(rd_workspace** out, int device) {
 }
 
 std::map<std::pair<int, hipStream_t>, rd_workspace*> g_default_ws;
+
+// ---- allocation-free scratch (rd_reduce_noalloc) ---------------------------
+//
+// One array per GPU, loaded with the library's code object and held until the
+// process ends: a 256-byte head (word 0: completion counter, word 1: the
+// sticky wait-status word, as in a workspace) followed by the tagged partial
+// words of up to kNoAllocGroups work-groups.  The host must never pass the
+// array's name to a kernel or a copy (on the host it is only a stand-in): its
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and every use goes through that address.
+constexpr int kNoAllocGroups = 4096;
+constexpr size_t kNoAllocHeadWords = 32;  // 256 bytes
+constexpr size_t kNoAllocWords = kNoAllocHeadWords + (size_t)kNoAllocGroups * rd::kPartialWords;
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+struct NoAllocDevice {
+  bool ready = false;
+  int cus = 0;
+  uint64_t* ptr = nullptr;  // device address of `scratch` on this device
+};
+constexpr int kNoAllocMaxDevices = 64;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];  // fixed table: set-up allocates nothing
+std::mutex g_noalloc_mu;
+
+// Resolve (once per device) the device address of `scratch` on `dev`, which
+// must be the current device.
+rd_status noalloc_setup(int dev, NoAllocDevice* out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(RD_ERR_INVALID_ARG, "rd_reduce_noalloc: device %d outside 0..%d", dev, kNoAllocMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc[dev];
+  if (!d.ready) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(RD_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    d.cus = cus > 0 ? cus : 1;
+    d.ptr = (uint64_t*)p;
+    d.ready = true;
+  }
+  *out = d;
+  return RD_OK;
+}
+
+// Re-arm the scratch for one launch of `groups` work-groups (plus the probe
+// slot): zero the completion counter and the partial slots.  A kernel, not
+// hipMemsetAsync, so the call can be captured in a HIP graph; the sticky
+// status word is left for rd_workspace_status.
+__global__ void noalloc_rearm(uint64_t* words, int64_t partial_words) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ((unsigned*)words)[0] = 0u;
+  uint64_t* partial = words + kNoAllocHeadWords;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < partial_words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    partial[i] = 0ull;
+}
 
 // Resolve the caller's workspace or the default one for (device, stream).
 rd_status resolve_workspace(rd_workspace* given, int device, hipStream_t s, rd_workspace** ws) {
@@ -389,7 +446,10 @@ extern "C" {
 rd_status rd_init(void) {
   int dev;
   DeviceInfo info;
-  return current_device(&dev, &info);
+  rd_status st = current_device(&dev, &info);
+  if (st != RD_OK) return st;
+  NoAllocDevice d;
+  return noalloc_setup(dev, &d);
 }
 
 size_t rd_dtype_size(rd_dtype dt) {
@@ -459,6 +519,24 @@ rd_status rd_workspace_status(rd_workspace* ws, unsigned* flags) {
         (scan_word && (e = hipMemcpy(w->scratch.scan_ctl + 3, &zero, 4, hipMemcpyHostToDevice)) != hipSuccess))
       return hip_fail(e, "rd_workspace_status: clear");
   }
+  if (!ws && dev >= 0 && dev < kNoAllocMaxDevices) {  // the allocation-free scratch of this device
+    NoAllocDevice d;
+    {
+      std::lock_guard<std::mutex> lock(g_noalloc_mu);
+      d = g_noalloc[dev];
+    }
+    if (d.ready) {
+      unsigned* status = (unsigned*)d.ptr + 1;
+      unsigned word = 0;
+      if ((e = hipMemcpy(&word, status, 4, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "rd_workspace_status: read");
+      if (word) {
+        f |= RD_WAIT_GRID;
+        if ((e = hipMemcpy(status, &zero, 4, hipMemcpyHostToDevice)) != hipSuccess)
+          return hip_fail(e, "rd_workspace_status: clear");
+      }
+    }
+  }
   *flags = f;
   return RD_OK;
 }
@@ -499,6 +577,46 @@ rd_status rd_reduce(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out, 
   l.probe = probe;
   hipError_t e = fn(n > 0 ? x : out, n, out, w->scratch, l, (hipStream_t)stream);
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce launch");
+}
+
+rd_status rd_reduce_noalloc(const void* x, int64_t n, rd_dtype dt, rd_op op, void* out, void* stream) {
+  if (!valid_dtype(dt)) return fail(RD_ERR_INVALID_ARG, "rd_reduce_noalloc: invalid dtype %d", (int)dt);
+  if (!valid_op(op)) return fail(RD_ERR_INVALID_ARG, "rd_reduce_noalloc: invalid op %d", (int)op);
+  if (n < 0) return fail(RD_ERR_INVALID_ARG, "rd_reduce_noalloc: n = %lld < 0", (long long)n);
+  const size_t es = rd_dtype_size(dt);
+  rd_dtype odt;
+  rd_out_dtype(dt, op, &odt);
+  rd_status st;
+  if (n > 0 && (st = check_ptr(x, es, "x")) != RD_OK) return st;
+  if ((st = check_ptr(out, rd_dtype_size(odt), "out")) != RD_OK) return st;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  NoAllocDevice d;
+  if ((st = noalloc_setup(dev, &d)) != RD_OK) return st;
+  const rd_config cfg = choose_config(RD_KIND_PLAIN, dt, op, n);
+  rd::PlainFn fn = rd::plain_launcher(dt, op, cfg.unroll, cfg.nontemporal != 0);
+  if (!fn)
+    return fail(RD_ERR_UNSUPPORTED, "rd_reduce_noalloc: no kernel for dtype %d op %d unroll %d", (int)dt, (int)op,
+                cfg.unroll);
+  const int probe = g_probe.load();
+  rd::Launch l = plan(cfg, (n * (int64_t)es) / 16, d.cus, kNoAllocGroups - probe);
+  l.probe = probe;
+  // The grid is capped at the scratch's capacity above (the kernel loops over
+  // any n), so this cannot trigger; it guards the scratch bound itself.
+  if (l.grid < 1 || l.grid + probe > kNoAllocGroups)
+    return fail(RD_ERR_INVALID_ARG, "rd_reduce_noalloc: %d work-groups exceed the scratch's %d", l.grid,
+                kNoAllocGroups);
+  rd::Scratch sc{};
+  sc.ticket = (unsigned*)d.ptr;
+  sc.partial = d.ptr + kNoAllocHeadWords;
+  sc.partial_cap = kNoAllocGroups;
+  const int64_t words = (int64_t)(l.grid + probe) * rd::kPartialWords;
+  hipLaunchKernelGGL(noalloc_rearm, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d.ptr,
+                     words);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "rd_reduce_noalloc: re-arm launch");
+  e = fn(n > 0 ? x : out, n, out, sc, l, (hipStream_t)stream);
+  return e == hipSuccess ? RD_OK : hip_fail(e, "rd_reduce_noalloc launch");
 }
 
 rd_status rd_reduce_compensated(const void* x, int64_t n, rd_dtype dt, double* out, rd_workspace* ws,
@@ -711,6 +829,6 @@ rd_status rd_tune_load(const char* path) {
   return RD_OK;
 }
 
-const char* rd_last_error(void) { return g_last_error.c_str(); }
+const char* rd_last_error(void) { return g_last_error; }
 
 }  // extern "C"

@@ -30,7 +30,8 @@ int main(int argc, char** argv) {
     CHECK(strstr(rd_last_error(), "n = -1") != NULL);
     CHECK(rd_reduce(NULL, 4, RD_F32, RD_SUM, fake, NULL, NULL) == RD_ERR_INVALID_ARG);
     CHECK(rd_reduce((void*)(uintptr_t)0x10001, 4, RD_F32, RD_SUM, fake, NULL, NULL) == RD_ERR_INVALID_ARG);
-    CHECK(rd_reduce(fake, 5, RD_I32, (rd_op)12, fake, NULL, NULL) == RD_ERR_INVALID_ARG);
+    CHECK(rd_reduce_noalloc(fake, -5, RD_I32, RD_XOR, fake, NULL) == RD_ERR_INVALID_ARG);
+    CHECK(rd_reduce_noalloc(fake, 5, RD_I32, (rd_op)12, fake, NULL) == RD_ERR_INVALID_ARG);
     CHECK(rd_reduce_compensated(fake, 4, RD_I32, (double*)fake, NULL, NULL) == RD_ERR_UNSUPPORTED);
     CHECK(rd_segmented_reduce(fake, (const int64_t*)fake, -1, RD_F32, RD_SUM, fake, NULL, NULL) ==
           RD_ERR_INVALID_ARG);

@@ -111,6 +111,10 @@ def test_host_errors_before_any_device_call(N):
     assert lib.rd_reduce(ctypes.c_void_p(0x10001), 4, N.RD_F32, N.RD_SUM, fake, None, None) == N.RD_ERR_INVALID_ARG
     assert b"aligned" in lib.rd_last_error()
     assert lib.rd_reduce(fake, 4, N.RD_F32, N.RD_SUM, None, None, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_reduce_noalloc(fake, -1, N.RD_F32, N.RD_SUM, fake, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_reduce_noalloc(fake, 4, 17, N.RD_SUM, fake, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_reduce_noalloc(None, 4, N.RD_F32, N.RD_SUM, fake, None) == N.RD_ERR_INVALID_ARG
+    assert lib.rd_reduce_noalloc(fake, 4, N.RD_F32, N.RD_SUM, ctypes.c_void_p(0x10002), None) == N.RD_ERR_INVALID_ARG
     assert lib.rd_reduce_compensated(fake, 4, N.RD_I32, fake, None, None) == N.RD_ERR_UNSUPPORTED
     assert lib.rd_reduce_compensated(fake, 4, N.RD_F64, fake, None, None) == N.RD_ERR_UNSUPPORTED
     assert lib.rd_segmented_reduce(fake, fake, -1, N.RD_F32, N.RD_SUM, fake, None, None) == N.RD_ERR_INVALID_ARG
