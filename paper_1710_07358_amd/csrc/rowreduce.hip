@@ -402,92 +402,74 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 // + 3 of the chunk, so every load and store instruction of a wavefront is
 // one contiguous kilobyte, and the chunk is the concatenation, in column
 // order, of 64 wavefront pieces (stripe-major, then wavefront).
-//   Rows with zeros are write-only: g * (product of the nonzero entries) at
-//   the single zero of a row with one; every other column's product of the
-//   other entries holds a zero, so it is g * 0 -- or NaN (IEEE 0 * inf) when
-//   those other entries hold an infinity or a NaN, which the forward's count
-//   of non-finite entries tells.
+//   Rows with zeros are write-only (see the loop below).
 //   Zero-free rows: grad[j] = K * P<(j) * P>(j), where K = g * (product of
 //   the chunks before) * (product of the chunks after), formed in float64
 //   from the forward's saved state, and P<, P> are the exclusive products
 //   inside the chunk: inside the work-item (4 columns), over the lanes of the
-//   piece (DPP scans), and over the pieces (one wavefront scans the 64 piece
-//   products in LDS).  No division anywhere.
+//   piece (DPP scans), and over the pieces (every wavefront scans the 64
+//   piece products from LDS).  No division anywhere.
 constexpr int kProdBlock = 1024;
 constexpr int kProdWaves = kProdBlock / 64;
 constexpr int kProdStripes = (int)(kChunk / (kProdBlock * 4));
 static_assert(kProdStripes * kProdWaves == 64, "one wavefront scans the chunk's pieces");
 
 // Two work-groups per CU (8 wavefronts per SIMD): at most 64 VGPRs.
+// Persistent: work-group w takes the tiles w, w + G, w + 2G, ... (G groups).
+// Every wavefront reads the row headers (and g) of 64 of those tiles at once,
+// one per lane, so the header latency is paid once per 64 tiles; each tile
+// then reads its fields from the lane that holds them.  Tiles of rows with
+// zeros are stores only.  For zero-free rows the next tile's x is loaded
+// before the current tile is processed (the last tile of a batch of 64 is
+// peeled, so every prefetch is unconditional), and a tile needs one barrier:
+// every wavefront scans the 64 piece products itself.
 template <bool AL, bool NT>
 __global__ __launch_bounds__(kProdBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g, const void* __restrict__ saved,
                          int64_t rows, int64_t cols, int64_t nch, double inv_nch, float* __restrict__ grad) {
-  __shared__ float lds_piece[64];               // piece products, column order
-  __shared__ float lds_before[64], lds_after[64];  // exclusive products over the pieces
-  __shared__ float lds_k;
+  __shared__ float lds_piece[2][64];  // piece products in column order, one array per tile parity
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const ProdHeader* __restrict__ hdr = (const ProdHeader*)saved;
   const double* __restrict__ pre = prod_prefix((void*)saved, rows);
   const double* __restrict__ suf = prod_suffix((void*)saved, rows, nch);
-  const int64_t total = rows * nch;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {  // one pass unless the grid was capped
+  const int64_t total = rows * nch, G = gridDim.x;
+  const auto row_of = [&](int64_t b) {
     int64_t r = (int64_t)((double)b * inv_nch);  // b / nch, then corrected
     if (r * nch > b) --r;
     if ((r + 1) * nch <= b) ++r;
-    const int64_t k = b - r * nch;
-    const int64_t c0 = k * kChunk;
+    return r;
+  };
+  const auto load_tile = [&](int64_t b, float (&v)[kProdStripes][4]) {
+    const int64_t r = row_of(b), c0 = (b - r * nch) * kChunk;
     const bool full = c0 + kChunk <= cols;
-    const ProdHeader h = hdr[r];
-    const float gr = g[r];
-    float* __restrict__ grow = grad + r * cols;
-    if (h.zeros != 0) {  // the same for the whole work-group
-      const int64_t hot = h.zeros == 1 ? h.first_zero : -1;
-      const float hot_val = gr * h.pnz;
-      const float zero_val = gr * 0.0f;
-#pragma unroll
-      for (int s = 0; s < kProdStripes; ++s) {
-        const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
-        if (col >= cols) continue;
-        float o[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool nan_here = h.nonfinite == -2 || (h.nonfinite >= 0 && col + e != h.nonfinite);
-          o[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : zero_val);
-        }
-        store_stripe<AL, NT>(grow, col, cols, full, o);
-      }
-      continue;
-    }
-    const float* __restrict__ xrow = x + r * cols;
-    float v[kProdStripes][4];
 #pragma unroll
     for (int s = 0; s < kProdStripes; ++s)
-      load_stripe<AL, NT>(xrow, c0 + ((int64_t)s * kProdBlock + t) * 4, cols, full, 1.0f, v[s]);
+      load_stripe<AL, NT>(x + r * cols, c0 + ((int64_t)s * kProdBlock + t) * 4, cols, full, 1.0f, v[s]);
+  };
+  int parity = 0;
+  const auto process = [&](int64_t b, const float (&v)[kProdStripes][4]) {
+    const int64_t r = row_of(b), k = b - r * nch, c0 = k * kChunk;
+    const bool full = c0 + kChunk <= cols;
+    // the rest of the row (chunks before and after), times g, in float64
+    const float K = (float)((double)g[r] * pre[r * nch + k] * suf[r * nch + k]);
     float before[kProdStripes], after[kProdStripes];
 #pragma unroll
     for (int s = 0; s < kProdStripes; ++s) {
       const float m = (v[s][0] * v[s][1]) * (v[s][2] * v[s][3]);  // this work-item's 4 columns
       float all;
       wave_excl_products(m, &before[s], &after[s], &all);
-      if (lane == 0) lds_piece[s * kProdWaves + wave] = all;
+      if (lane == 0) lds_piece[parity][s * kProdWaves + wave] = all;
     }
     __syncthreads();
-    if (wave == 0) {
-      float pb, pa, pall;
-      wave_excl_products(lds_piece[lane], &pb, &pa, &pall);
-      lds_before[lane] = pb;
-      lds_after[lane] = pa;
-      if (lane == 0) lds_k = (float)((double)gr * pre[r * nch + k] * suf[r * nch + k]);
-    }
-    __syncthreads();
-    const float K = lds_k;
+    float pb, pa, pall;
+    wave_excl_products(lds_piece[parity][lane], &pb, &pa, &pall);
+    float* __restrict__ grow = grad + r * cols;
 #pragma unroll
     for (int s = 0; s < kProdStripes; ++s) {
-      const int piece = s * kProdWaves + wave;
-      const float left = (K * lds_before[piece]) * before[s];
-      const float right = after[s] * lds_after[piece];
+      const int piece = s * kProdWaves + wave;  // wavefront-uniform
+      const float left = (K * readlane(pb, piece)) * before[s];
+      const float right = after[s] * readlane(pa, piece);
       const float p01 = v[s][0] * v[s][1], p23 = v[s][2] * v[s][3];
       float o[4];
       o[0] = left * (v[s][1] * p23) * right;
@@ -497,7 +479,68 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
       const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
       if (col < cols) store_stripe<AL, NT>(grow, col, cols, full, o);
     }
-    __syncthreads();  // the LDS arrays are rewritten by the next tile
+    parity ^= 1;  // the next tile writes the other array: no second barrier
+  };
+  for (int64_t base = blockIdx.x; base < total; base += 64 * G) {
+    // lane j: the header and g of tile base + j * G (every wavefront the same)
+    const int64_t bj = base + (int64_t)lane * G;
+    const bool valid = bj < total;
+    ProdHeader hj{0, -1, 0.0f, -1};
+    float gj = 0.0f;
+    if (valid) {
+      const int64_t rj = row_of(bj);
+      hj = hdr[rj];
+      gj = g[rj];
+    }
+    uint64_t fills = __builtin_amdgcn_ballot_w64(valid && hj.zeros != 0);
+    uint64_t todo = __builtin_amdgcn_ballot_w64(valid && hj.zeros == 0);
+    // Rows with zeros: stores only, from the header -- g * (product of the
+    // nonzero entries) at the single zero of a row with one; every other
+    // column's product of the other entries holds a zero, so it is g * 0, or
+    // NaN (IEEE 0 * inf) when those other entries hold an infinity or a NaN.
+    while (fills != 0ull) {
+      const int j = __builtin_ctzll(fills);
+      fills &= fills - 1ull;
+      const int64_t b = base + (int64_t)j * G;
+      const int64_t r = row_of(b), c0 = (b - r * nch) * kChunk;
+      const bool full = c0 + kChunk <= cols;
+      const int32_t zeros = readlane(hj.zeros, j), nonfinite = readlane(hj.nonfinite, j);
+      const float gr = readlane(gj, j);
+      const int64_t hot = zeros == 1 ? (int64_t)readlane(hj.first_zero, j) : -1;
+      const float hot_val = gr * readlane(hj.pnz, j), zero_val = gr * 0.0f;
+      float* __restrict__ grow = grad + r * cols;
+#pragma unroll
+      for (int s = 0; s < kProdStripes; ++s) {
+        const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
+        if (col >= cols) continue;
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool nan_here = nonfinite == -2 || (nonfinite >= 0 && col + e != nonfinite);
+          o[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : zero_val);
+        }
+        store_stripe<AL, NT>(grow, col, cols, full, o);
+      }
+    }
+    if (todo == 0ull) continue;
+    // Zero-free rows: the exclusive products, the next tile's x loaded early.
+    float cur[kProdStripes][4];
+    int64_t b = base + (int64_t)__builtin_ctzll(todo) * G;
+    todo &= todo - 1ull;
+    load_tile(b, cur);
+    while (todo != 0ull) {
+      const int64_t bn = base + (int64_t)__builtin_ctzll(todo) * G;
+      todo &= todo - 1ull;
+      float nxt[kProdStripes][4];
+      load_tile(bn, nxt);
+      process(b, cur);
+#pragma unroll
+      for (int s = 0; s < kProdStripes; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cur[s][e] = nxt[s][e];
+      b = bn;
+    }
+    process(b, cur);
   }
 }
 
@@ -596,9 +639,9 @@ hipError_t fill_launch(const float* g, const void* saved, int64_t rows, int64_t 
 
 template <bool AL>
 hipError_t prod_bwd_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                           float* grad, bool nt, hipStream_t s) {
+                           float* grad, int cus, bool nt, hipStream_t s) {
   const int64_t nch = chunks_of(cols);
-  const int64_t blocks = std::min<int64_t>(rows * nch, (int64_t)1 << 30);
+  const int64_t blocks = std::min<int64_t>(rows * nch, (int64_t)cus * 2);  // persistent: two per CU
   const double inv = 1.0 / (double)nch;
   if (nt) hipLaunchKernelGGL((row_prod_bwd_kernel<AL, true>), dim3((unsigned)blocks), dim3(kProdBlock), 0, s, x, g,
                              saved, rows, cols, nch, inv, grad);
@@ -609,10 +652,10 @@ hipError_t prod_bwd_launch(const float* x, const float* g, const void* saved, in
 
 template <Op O>
 hipError_t bwd_op(bool al, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                  float* grad, bool nt, hipStream_t s) {
+                  float* grad, int cus, bool nt, hipStream_t s) {
   if constexpr (O == Op::Prod) {
-    return al ? prod_bwd_launch<true>(x, g, saved, rows, cols, grad, nt, s)
-              : prod_bwd_launch<false>(x, g, saved, rows, cols, grad, nt, s);
+    return al ? prod_bwd_launch<true>(x, g, saved, rows, cols, grad, cus, nt, s)
+              : prod_bwd_launch<false>(x, g, saved, rows, cols, grad, cus, nt, s);
   } else {
     return al ? fill_launch<O, true>(g, saved, rows, cols, grad, nt, s)
               : fill_launch<O, false>(g, saved, rows, cols, grad, nt, s);
@@ -635,13 +678,12 @@ hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, f
 
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, rd_op op,
                          float* grad, int cus, const Launch& l, hipStream_t s) {
-  (void)cus;  // flat grids over (row, tile): no persistent grid to size
   const bool al = (cols % 4 == 0) && ((uintptr_t)grad % 16 == 0) && (op != RD_PROD || (uintptr_t)x % 16 == 0);
   switch (op) {
-    case RD_SUM: return bwd_op<Op::Sum>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
-    case RD_MAX: return bwd_op<Op::Max>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
-    case RD_MIN: return bwd_op<Op::Min>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
-    case RD_PROD: return bwd_op<Op::Prod>(al, x, g, saved, rows, cols, grad, l.nontemporal, s);
+    case RD_SUM: return bwd_op<Op::Sum>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s);
+    case RD_MAX: return bwd_op<Op::Max>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s);
+    case RD_MIN: return bwd_op<Op::Min>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s);
+    case RD_PROD: return bwd_op<Op::Prod>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s);
     default: return hipErrorInvalidValue;
   }
 }
