@@ -240,22 +240,33 @@ __global__ __launch_bounds__(1024) void segmented_kernel(const typename R::T* __
   // segments they belong to.  Span = [P0, wend).
   auto consume = [&](const A (&vals)[K], auto rel, int64_t P0, int64_t wend) {
     int64_t consumed = P0;
+    bool carried = true;  // acc[] holds segment s's piece from earlier windows until s ends here
     while (seg_end < wend) {
-      const int32_t from = (int32_t)(consumed - P0), bound = (int32_t)(seg_end - P0);
+      // This lane's part of segment s: the carried piece (at s's end only),
+      // then the elements at window-relative positions [from, from + len),
+      // tested with one unsigned compare each.
+      const uint32_t from = (uint32_t)(consumed - P0), len = (uint32_t)(seg_end - consumed);
+      A lane_v = R::identity();
+      if (carried) {
+        lane_v = acc[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) lane_v = R::apply(lane_v, acc[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] = R::identity();
+        carried = false;
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int32_t q = rel(k);
-        const A v = (q >= from && q < bound) ? vals[k] : R::identity();
-        acc[k] = R::apply(acc[k], v);
+        const uint32_t q = (uint32_t)rel(k) - from;
+        lane_v = R::apply(lane_v, q < len ? vals[k] : R::identity());
       }
-      emit(s, fold_acc(), seg_begin, seg_end);
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] = R::identity();
+      emit(s, wave_reduce_r<R>(lane_v), seg_begin, seg_end);
       consumed = seg_end;
       s = next_segment(s, seg_end);
       seg_begin = consumed;
       seg_end = offset_at(s + 1);
     }
+    // The piece of the segment that runs on joins the accumulators.
     const int32_t from = (int32_t)(consumed - P0);
     if (from == 0) {
 #pragma unroll
