@@ -19,13 +19,12 @@
 //   max/min -> g[r] at the saved column, 0 elsewhere (write-only);
 //   product -> rows with >= 2 zeros: 0; one zero: g*prod(nonzeros) at the
 //              zero, 0 elsewhere (IEEE NaN where the other entries pair a
-//              zero with an infinity or NaN); no zero:
-//              g * prod_{i<j} x * prod_{i>j} x.  One
-//              work-group per (row, chunk) over a flat grid: the chunk's own
-//              exclusive prefix and suffix products come from DPP scans over
-//              the lanes and one scan over the chunk's 64 wavefront pieces,
-//              the rest of the row from the saved chunk prefix/suffix -- no
-//              division, every tile independent.
+//              zero with an infinity or NaN) -- the store-only fill shape;
+//              no zero: g * prod_{i<j} x * prod_{i>j} x, a persistent launch
+//              over (row, chunk) tiles: the chunk's own exclusive prefix and
+//              suffix products come from DPP scans over the lanes and over
+//              the chunk's 64 wavefront pieces, the rest of the row from the
+//              saved chunk prefix/suffix -- no division.
 #include "rd_device.hpp"
 #include "rd_internal.hpp"
 
@@ -402,7 +401,7 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 // + 3 of the chunk, so every load and store instruction of a wavefront is
 // one contiguous kilobyte, and the chunk is the concatenation, in column
 // order, of 64 wavefront pieces (stripe-major, then wavefront).
-//   Rows with zeros are write-only (see the loop below).
+//   Rows with zeros are write-only: row_fill_kernel<Prod> writes them.
 //   Zero-free rows: grad[j] = K * P<(j) * P>(j), where K = g * (product of
 //   the chunks before) * (product of the chunks after), formed in float64
 //   from the forward's saved state, and P<, P> are the exclusive products
@@ -417,12 +416,12 @@ static_assert(kProdStripes * kProdWaves == 64, "one wavefront scans the chunk's 
 // Two work-groups per CU (8 wavefronts per SIMD): at most 64 VGPRs.
 // Persistent: work-group w takes the tiles w, w + G, w + 2G, ... (G groups).
 // Every wavefront reads the row headers (and g) of 64 of those tiles at once,
-// one per lane, so the header latency is paid once per 64 tiles; each tile
-// then reads its fields from the lane that holds them.  Tiles of rows with
-// zeros are stores only.  For zero-free rows the next tile's x is loaded
-// before the current tile is processed (the last tile of a batch of 64 is
-// peeled, so every prefetch is unconditional), and a tile needs one barrier:
-// every wavefront scans the 64 piece products itself.
+// one per lane, so tiles of rows with zeros -- written by
+// row_fill_kernel<Prod> -- are skipped at one shared load per 64.  For
+// zero-free rows the next tile's x is loaded before the current tile is
+// processed (the last tile of a batch of 64 is peeled, so every prefetch is
+// unconditional), and a tile needs one barrier: every wavefront scans the 64
+// piece products itself.
 template <bool AL, bool NT>
 __global__ __launch_bounds__(kProdBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g, const void* __restrict__ saved,
@@ -482,46 +481,12 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
     parity ^= 1;  // the next tile writes the other array: no second barrier
   };
   for (int64_t base = blockIdx.x; base < total; base += 64 * G) {
-    // lane j: the header and g of tile base + j * G (every wavefront the same)
+    // lane j: the zero count of tile base + j * G's row (every wavefront the same)
     const int64_t bj = base + (int64_t)lane * G;
     const bool valid = bj < total;
-    ProdHeader hj{0, -1, 0.0f, -1};
-    float gj = 0.0f;
-    if (valid) {
-      const int64_t rj = row_of(bj);
-      hj = hdr[rj];
-      gj = g[rj];
-    }
-    uint64_t fills = __builtin_amdgcn_ballot_w64(valid && hj.zeros != 0);
-    uint64_t todo = __builtin_amdgcn_ballot_w64(valid && hj.zeros == 0);
-    // Rows with zeros: stores only, from the header -- g * (product of the
-    // nonzero entries) at the single zero of a row with one; every other
-    // column's product of the other entries holds a zero, so it is g * 0, or
-    // NaN (IEEE 0 * inf) when those other entries hold an infinity or a NaN.
-    while (fills != 0ull) {
-      const int j = __builtin_ctzll(fills);
-      fills &= fills - 1ull;
-      const int64_t b = base + (int64_t)j * G;
-      const int64_t r = row_of(b), c0 = (b - r * nch) * kChunk;
-      const bool full = c0 + kChunk <= cols;
-      const int32_t zeros = readlane(hj.zeros, j), nonfinite = readlane(hj.nonfinite, j);
-      const float gr = readlane(gj, j);
-      const int64_t hot = zeros == 1 ? (int64_t)readlane(hj.first_zero, j) : -1;
-      const float hot_val = gr * readlane(hj.pnz, j), zero_val = gr * 0.0f;
-      float* __restrict__ grow = grad + r * cols;
-#pragma unroll
-      for (int s = 0; s < kProdStripes; ++s) {
-        const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
-        if (col >= cols) continue;
-        float o[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool nan_here = nonfinite == -2 || (nonfinite >= 0 && col + e != nonfinite);
-          o[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : zero_val);
-        }
-        store_stripe<AL, NT>(grow, col, cols, full, o);
-      }
-    }
+    int32_t zj = 1;
+    if (valid) zj = hdr[row_of(bj)].zeros;
+    uint64_t todo = __builtin_amdgcn_ballot_w64(valid && zj == 0);
     if (todo == 0ull) continue;
     // Zero-free rows: the exclusive products, the next tile's x loaded early.
     float cur[kProdStripes][4];
@@ -544,11 +509,18 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
   }
 }
 
-// Write-only gradients (sum; min/max), one tile of kRowBlock x 4 columns per
-// work-group and one 16-byte store per work-item, over a flat grid of
-// rows x tiles: for pure writes, many short work-groups keep more stores in
-// flight than a persistent loop (measured on MI355X: 6.9 TB/s against
-// 6.2 TB/s).
+// Write-only gradients (sum; min/max; product rows with zeros), one tile of
+// kRowBlock x 4 columns per work-group and one 16-byte store per work-item,
+// over a flat grid of rows x tiles: for pure writes, many short work-groups
+// keep more stores in flight than a persistent loop (measured on MI355X:
+// 6.9 TB/s against 6.2 TB/s; product rows with zeros 0.60 ms against 0.96 ms
+// for a persistent loop and 0.82 ms inside the exclusive-product kernel).
+//   Product rows with zeros: g * (product of the nonzero entries) at the
+//   single zero of a row with one; every other column's product of the other
+//   entries holds a zero, so it is g * 0 -- or NaN (IEEE 0 * inf) when those
+//   other entries hold an infinity or a NaN, which the forward's record of
+//   non-finite entries tells.  Work-groups of zero-free rows leave (the
+//   exclusive-product kernel writes those rows).
 template <Op O, bool AL, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_fill_kernel(const float* __restrict__ g,
                                                              const void* __restrict__ saved, int64_t rows,
@@ -564,16 +536,26 @@ __global__ __launch_bounds__(kRowBlock) void row_fill_kernel(const float* __rest
     const float gr = g[r];
     int64_t hot = -1;
     float hot_val = 0.0f, fill = 0.0f;
-    static_assert(O == Op::Sum || O == Op::Max || O == Op::Min, "the product has its own kernel");
+    int32_t nonfinite = -1;
     if constexpr (O == Op::Sum) {
       fill = gr;
+    } else if constexpr (O == Op::Prod) {
+      const ProdHeader h = ((const ProdHeader*)saved)[r];
+      if (h.zeros == 0) continue;  // the same for the whole work-group
+      hot = h.zeros == 1 ? h.first_zero : -1;
+      hot_val = gr * h.pnz;
+      fill = gr * 0.0f;
+      nonfinite = h.nonfinite;
     } else {
       hot = ((const int64_t*)saved)[r];
       hot_val = gr;
     }
     float v[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (col + e == hot) ? hot_val : fill;
+    for (int e = 0; e < 4; ++e) {
+      const bool nan_here = nonfinite == -2 || (nonfinite >= 0 && col + e != nonfinite);
+      v[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : fill);
+    }
     store_stripe<AL, NT>(grad + r * cols, col, cols, col + 4 <= cols, v);
   }
 }
@@ -653,7 +635,10 @@ hipError_t prod_bwd_launch(const float* x, const float* g, const void* saved, in
 template <Op O>
 hipError_t bwd_op(bool al, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
                   float* grad, int cus, bool nt, hipStream_t s) {
-  if constexpr (O == Op::Prod) {
+  if constexpr (O == Op::Prod) {  // rows with zeros, then zero-free rows: disjoint rows, any order
+    hipError_t e = al ? fill_launch<O, true>(g, saved, rows, cols, grad, nt, s)
+                      : fill_launch<O, false>(g, saved, rows, cols, grad, nt, s);
+    if (e != hipSuccess) return e;
     return al ? prod_bwd_launch<true>(x, g, saved, rows, cols, grad, cus, nt, s)
               : prod_bwd_launch<false>(x, g, saved, rows, cols, grad, cus, nt, s);
   } else {
