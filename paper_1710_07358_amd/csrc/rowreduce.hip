@@ -509,12 +509,36 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
   }
 }
 
+// Division of a work-group index by a launch constant d (1 <= d < 2^31),
+// exact for every 32-bit dividend, with one multiply-high, a subtraction and
+// shifts (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994: the round-down method with an added correction).
+// The host computes m, s1 and s2 once per launch.
+struct DivMagic {
+  uint32_t m, s1, s2;
+};
+inline DivMagic div_magic(uint32_t d) {
+  uint32_t l = 0;  // ceil(log2 d)
+  while ((1ull << l) < d) ++l;
+  return DivMagic{(uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l < 1 ? l : 1u, l > 0 ? l - 1 : 0u};
+}
+__device__ __forceinline__ uint32_t div_by(uint32_t n, DivMagic q) {
+  const uint32_t t = __umulhi(n, q.m);
+  return (t + ((n - t) >> q.s1)) >> q.s2;
+}
+
 // Write-only gradients (sum; min/max; product rows with zeros), one tile of
 // kRowBlock x 4 columns per work-group and one 16-byte store per work-item,
 // over a flat grid of rows x tiles: for pure writes, many short work-groups
 // keep more stores in flight than a persistent loop (measured on MI355X:
 // 6.9 TB/s against 6.2 TB/s; product rows with zeros 0.60 ms against 0.96 ms
 // for a persistent loop and 0.82 ms inside the exclusive-product kernel).
+// The row comes from the work-group index by one multiply-high on the scalar
+// unit, so a work-group with nothing to write leaves after a kernel-argument
+// load and one header load: with a float64 division and a grid-stride loop
+// instead, a zero-free 4096 x 262,144 product matrix took 0.39 ms to
+// dispatch and retire its 4 M wavefronts, against 0.22 ms now (a bare
+// load-and-leave kernel over the same grid: 0.23 ms).
 //   Product rows with zeros: g * (product of the nonzero entries) at the
 //   single zero of a row with one; every other column's product of the other
 //   entries holds a zero, so it is g * 0 -- or NaN (IEEE 0 * inf) when those
@@ -523,41 +547,45 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
 //   exclusive-product kernel writes those rows).
 template <Op O, bool AL, bool NT>
 __global__ __launch_bounds__(kRowBlock) void row_fill_kernel(const float* __restrict__ g,
-                                                             const void* __restrict__ saved, int64_t rows,
-                                                             int64_t cols, int64_t tiles, double inv_tiles,
+                                                             const void* __restrict__ saved, int64_t row0,
+                                                             int64_t cols, uint32_t tiles, DivMagic dm,
                                                              float* __restrict__ grad) {
-  const int64_t total = rows * tiles;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {  // one pass unless the grid was capped
-    int64_t r = (int64_t)((double)b * inv_tiles);  // b / tiles, then corrected
-    if (r * tiles > b) --r;
-    if ((r + 1) * tiles <= b) ++r;
-    const int64_t col = (b - r * tiles) * (kRowBlock * 4) + (int64_t)threadIdx.x * 4;
-    if (col >= cols) continue;
-    const float gr = g[r];
-    int64_t hot = -1;
-    float hot_val = 0.0f, fill = 0.0f;
-    int32_t nonfinite = -1;
-    if constexpr (O == Op::Sum) {
-      fill = gr;
-    } else if constexpr (O == Op::Prod) {
-      const ProdHeader h = ((const ProdHeader*)saved)[r];
-      if (h.zeros == 0) continue;  // the same for the whole work-group
-      hot = h.zeros == 1 ? h.first_zero : -1;
-      hot_val = gr * h.pnz;
-      fill = gr * 0.0f;
-      nonfinite = h.nonfinite;
-    } else {
-      hot = ((const int64_t*)saved)[r];
-      hot_val = gr;
-    }
-    float v[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const bool nan_here = nonfinite == -2 || (nonfinite >= 0 && col + e != nonfinite);
-      v[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : fill);
-    }
-    store_stripe<AL, NT>(grad + r * cols, col, cols, col + 4 <= cols, v);
+  // The launch covers rows row0 .. row0 + gridDim.x / tiles - 1, tiles work-groups each.
+  const uint32_t b = blockIdx.x, rb = div_by(b, dm);
+  const int64_t r = row0 + rb;
+  const float gr = g[r];
+  int64_t hot = -1;
+  float hot_val = 0.0f, fill = 0.0f;
+  int32_t nonfinite = -1;
+  if constexpr (O == Op::Prod) {
+    const ProdHeader h = ((const ProdHeader*)saved)[r];
+    if (h.zeros == 0) return;  // the same for the whole work-group
+    hot = h.zeros == 1 ? h.first_zero : -1;
+    hot_val = gr * h.pnz;
+    fill = gr * 0.0f;
+    nonfinite = h.nonfinite;
+  } else if constexpr (O == Op::Sum) {
+    fill = gr;
+  } else {
+    hot = ((const int64_t*)saved)[r];
+    hot_val = gr;
   }
+  // A writing wavefront waits about 1000-1300 cycles before its store.  The
+  // write stream runs faster when each work-group stays resident that much
+  // longer (measured on MI355X over a 4096 x 262,144 matrix: sum 636 -> 597,
+  // max 638 -> 597, product 625 -> 595 us); past the best length the wait
+  // itself limits the rate (product at 22 units: 622 us, at 32: 757 us), and
+  // the product's own longer path reaches that point first.
+  __builtin_amdgcn_s_sleep(O == Op::Prod ? 16 : 20);
+  const int64_t col = (int64_t)(b - rb * tiles) * (kRowBlock * 4) + (int64_t)threadIdx.x * 4;
+  if (col >= cols) return;
+  float v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bool nan_here = nonfinite == -2 || (nonfinite >= 0 && col + e != nonfinite);
+    v[e] = (col + e == hot) ? hot_val : (nan_here ? __builtin_nanf("") : fill);
+  }
+  store_stripe<AL, NT>(grad + r * cols, col, cols, col + 4 <= cols, v);
 }
 
 // ------------------------------------------------------------------ host side
@@ -573,6 +601,8 @@ size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
 }
 
 namespace {
+constexpr int64_t kFillBlocks = (int64_t)1 << 22;  // work-groups per fill launch (rows x tiles), at most
+
 // Persistent grid over rows: blocks_per_cu work-groups per CU.
 int row_grid(int64_t rows, int cus, int bpc) {
   const int64_t g = (int64_t)cus * bpc;
@@ -609,14 +639,19 @@ hipError_t fwd_op(bool al, int S, const float* x, int64_t rows, int64_t cols, fl
 template <Op O, bool AL>
 hipError_t fill_launch(const float* g, const void* saved, int64_t rows, int64_t cols, float* grad, bool nt,
                        hipStream_t s) {
-  const int64_t tiles = (cols + kRowBlock * 4 - 1) / (kRowBlock * 4);
-  const int64_t blocks = std::min<int64_t>(rows * tiles, (int64_t)1 << 30);
-  const double inv = 1.0 / (double)tiles;
-  if (nt) hipLaunchKernelGGL((row_fill_kernel<O, AL, true>), dim3((unsigned)blocks), dim3(kRowBlock), 0, s, g, saved,
-                             rows, cols, tiles, inv, grad);
-  else hipLaunchKernelGGL((row_fill_kernel<O, AL, false>), dim3((unsigned)blocks), dim3(kRowBlock), 0, s, g, saved,
-                          rows, cols, tiles, inv, grad);
-  return hipGetLastError();
+  const int64_t tiles = (cols + kRowBlock * 4 - 1) / (kRowBlock * 4);  // cols < 2^31: at most 2^21 tiles
+  const int64_t per = std::max<int64_t>(1, kFillBlocks / tiles);      // rows per launch
+  const DivMagic dm = div_magic((uint32_t)tiles);
+  for (int64_t row0 = 0; row0 < rows; row0 += per) {
+    const unsigned blocks = (unsigned)(std::min<int64_t>(rows - row0, per) * tiles);
+    if (nt) hipLaunchKernelGGL((row_fill_kernel<O, AL, true>), dim3(blocks), dim3(kRowBlock), 0, s, g, saved, row0, cols,
+                               (uint32_t)tiles, dm, grad);
+    else hipLaunchKernelGGL((row_fill_kernel<O, AL, false>), dim3(blocks), dim3(kRowBlock), 0, s, g, saved, row0, cols,
+                            (uint32_t)tiles, dm, grad);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <bool AL>
