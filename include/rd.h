@@ -320,7 +320,13 @@ rd_status rd_rowreduce_fwd(const void* x, int64_t rows, int64_t cols, rd_dtype d
  *              at the zero and 0 elsewhere; rows with two or more zeros get 0.
  *   x       : the forward input (read only for product rows without zeros)
  *   g       : device float32[rows];  saved : as filled by rd_rowreduce_fwd
- *   grad_in : device float32[rows, cols] */
+ *   grad_in : device float32[rows, cols]
+ * The product writes its rows with zeros on a second stream that the library
+ * creates once per device (default priority) and keeps until the process
+ * ends: forked from `stream` by an event and joined back into it, so the
+ * call's work still lies between the work enqueued on `stream` before and
+ * after it (also under graph capture).  Concurrent calls on one device are
+ * serialised while they enqueue. */
 rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int64_t rows,
                            int64_t cols, rd_dtype dt, rd_op op, void* grad_in, void* stream);
 

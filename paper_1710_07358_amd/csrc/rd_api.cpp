@@ -443,13 +443,50 @@ rd_status scan_call(const char* name, const void* x, int64_t n, const int64_t* h
 
 extern "C" {
 
+// ---- side stream of the product backward ----------------------------------
+
+// Per device: a second stream (default priority, non-blocking) and two events
+// for the product backward's fork and join, created once and kept until the
+// process ends.  The mutex keeps one caller's record / wait / launch / record
+// / wait sequence whole, so concurrent callers never wait on each other's
+// event records.  If creation fails the backward runs both kernels on the
+// caller's stream.
+constexpr int kSideMaxDevices = 64;
+struct SideDevice {
+  std::mutex mu;
+  bool tried = false;
+  rd::SidePath path;
+};
+SideDevice g_side[kSideMaxDevices];
+
+// With ss.mu held.
+void side_setup(SideDevice& ss) {
+  if (ss.tried) return;
+  ss.tried = true;
+  rd::SidePath p;
+  if (hipStreamCreateWithFlags(&p.stream, hipStreamNonBlocking) != hipSuccess) p.stream = nullptr;
+  if (p.stream && (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess ||
+                   hipEventCreateWithFlags(&p.join, hipEventDisableTiming) != hipSuccess)) {
+    if (p.fork) (void)hipEventDestroy(p.fork);
+    if (p.join) (void)hipEventDestroy(p.join);
+    (void)hipStreamDestroy(p.stream);
+    p = rd::SidePath{};
+  }
+  ss.path = p;
+}
+
 rd_status rd_init(void) {
   int dev;
   DeviceInfo info;
   rd_status st = current_device(&dev, &info);
   if (st != RD_OK) return st;
   NoAllocDevice d;
-  return noalloc_setup(dev, &d);
+  if ((st = noalloc_setup(dev, &d)) != RD_OK) return st;
+  if (dev >= 0 && dev < kSideMaxDevices) {
+    std::lock_guard<std::mutex> lock(g_side[dev].mu);
+    side_setup(g_side[dev]);
+  }
+  return RD_OK;
 }
 
 size_t rd_dtype_size(rd_dtype dt) {
@@ -771,8 +808,17 @@ rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int6
   DeviceInfo info;
   if ((st = current_device(&dev, &info)) != RD_OK) return st;
   const rd::Launch l = row_launch(RD_KIND_ROWWISE_BWD, op, rows, cols);
-  hipError_t e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in,
-                                   info.cus, l, (hipStream_t)stream);
+  hipError_t e;
+  if (op == RD_PROD && dev >= 0 && dev < kSideMaxDevices) {
+    SideDevice& ss = g_side[dev];
+    std::lock_guard<std::mutex> lock(ss.mu);
+    side_setup(ss);
+    e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in, info.cus, l,
+                          (hipStream_t)stream, ss.path);
+  } else {
+    e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in, info.cus, l,
+                          (hipStream_t)stream, rd::SidePath{});
+  }
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_bwd launch");
 }
 

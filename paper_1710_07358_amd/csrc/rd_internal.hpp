@@ -128,8 +128,16 @@ SegFn seg_half(rd_dtype dt, rd_op op, int unroll, bool nt);
 // (capped by rows), unroll = stripes per step (1, 2, 4, 8).
 hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, float* y,
                          void* saved, int cus, const Launch& l, hipStream_t s);
+// A second stream of the device and two events: the product backward runs
+// its exclusive-product kernel there, beside the fill on the caller's stream
+// (fork and join by the events).  Null stream: both run on the caller's.
+struct SidePath {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows,
-                         int64_t cols, rd_op op, float* grad, int cus, const Launch& l, hipStream_t s);
+                         int64_t cols, rd_op op, float* grad, int cus, const Launch& l, hipStream_t s,
+                         const SidePath& side);
 size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols);
 
 // The paper's two designs (sum of int32 / float32), for comparison:

@@ -272,3 +272,64 @@ def test_rowwise_full_shape_sampled_rows(op):
     check_backward(xs, op, g_np[sample], grad[sample])
     del x, grad
     torch.cuda.empty_cache()
+
+
+def _mixed_prod_rows(rows, cols, salt):
+    # every other row holds one zero (fill kernel), the others none (the
+    # exclusive-product kernel, which runs on the library's side stream)
+    x = W.rowwise(rows, cols, "prod", salt=salt)
+    x[x == 0] = np.float32(1.0)
+    x[::2, (77 + salt) % cols] = 0.0
+    return x
+
+
+def test_rowwise_prod_graph_replay_with_side_stream():
+    # forward and backward captured in one graph: the backward's fork to the
+    # side stream and its join back are captured with it; replays with new
+    # data, eager work between them
+    rows, cols = 12, 40_000
+    g_np = np.linspace(-2.0, 3.0, rows).astype(np.float32)
+    g = torch.from_numpy(g_np).cuda()
+    x = torch.empty(rows, cols, dtype=torch.float32, device="cuda")
+    x.copy_(torch.from_numpy(_mixed_prod_rows(rows, cols, 0)))
+    y, saved = rd.rowreduce_forward(x, "prod")  # eager calls before capture
+    rd.rowreduce_backward(x, g, saved, "prod")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            yg, sg = rd.rowreduce_forward(x, "prod")
+            gg = rd.rowreduce_backward(x, g, sg, "prod")
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        x_np = _mixed_prod_rows(rows, cols, rep + 1)
+        print(f"[rowwise] graph replay {rep}", flush=True)
+        x.copy_(torch.from_numpy(x_np))
+        graph.replay()
+        torch.cuda.synchronize()
+        check_forward(x_np, "prod", yg, sg)
+        check_backward(x_np, "prod", g_np, gg)
+        rd.reduce(x.view(-1), "sum")
+        torch.cuda.synchronize()
+
+
+def test_rowwise_prod_backward_two_caller_streams():
+    # two callers on two streams share the side stream: each call's join waits
+    # for its own exclusive-product launch
+    rows, cols = 10, 70_000
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    xs = [_mixed_prod_rows(rows, cols, 5), _mixed_prod_rows(rows, cols, 6)]
+    gs = [np.linspace(-1.0, 1.0, rows).astype(np.float32), np.linspace(2.0, -3.0, rows).astype(np.float32)]
+    xt = [torch.from_numpy(a).cuda() for a in xs]
+    gt = [torch.from_numpy(a).cuda() for a in gs]
+    torch.cuda.synchronize()
+    grads = []
+    for i, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            _, saved = rd.rowreduce_forward(xt[i], "prod")
+            grads.append(rd.rowreduce_backward(xt[i], gt[i], saved, "prod"))
+    torch.cuda.synchronize()
+    for i in range(2):
+        check_backward(xs[i], "prod", gs[i], grads[i])
