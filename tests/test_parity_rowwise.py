@@ -333,3 +333,22 @@ def test_rowwise_prod_backward_two_caller_streams():
     torch.cuda.synchronize()
     for i in range(2):
         check_backward(xs[i], "prod", gs[i], grads[i])
+
+
+@pytest.mark.parametrize("op", ["sum", "max", "prod"])
+def test_rowwise_backward_fill_over_several_launches(op):
+    # 2^22 + 3 one-column rows: more (row, tile) work-groups than one fill
+    # launch takes (2^22), so the fill runs as two launches, the second
+    # starting at a nonzero row
+    rows, cols = (1 << 22) + 3, 1
+    rng = np.random.default_rng(11)
+    x_np = rng.standard_normal((rows, cols)).astype(np.float32)
+    if op == "prod":
+        x_np[::3] = 0.0  # rows with a zero (fill) among zero-free rows (exclusive products)
+    g_np = rng.standard_normal(rows).astype(np.float32)
+    print(f"[rowwise] fill over several launches op={op} rows={rows}", flush=True)
+    x = torch.from_numpy(x_np).cuda()
+    _, saved = rd.rowreduce_forward(x, op)
+    grad = rd.rowreduce_backward(x, torch.from_numpy(g_np).cuda(), saved, op)
+    torch.cuda.synchronize()
+    check_backward(x_np, op, g_np, grad)
