@@ -145,6 +145,16 @@ rd_status create_workspace(rd_workspace** out, int device) {
 
 std::map<std::pair<int, hipStream_t>, rd_workspace*> g_default_ws;
 
+// create_workspace for callers that go on without one: a failure leaves the
+// thread's last-error message as it was.
+rd_status create_workspace_quiet(rd_workspace** out, int device) {
+  char saved[sizeof(g_last_error)];
+  std::memcpy(saved, g_last_error, sizeof(saved));
+  const rd_status st = create_workspace(out, device);
+  if (st != RD_OK) std::memcpy(g_last_error, saved, sizeof(saved));
+  return st;
+}
+
 // ---- allocation-free scratch (rd_reduce_noalloc) ---------------------------
 //
 // One array per GPU, loaded with the library's code object and held until the
@@ -201,6 +211,21 @@ __global__ void noalloc_rearm(uint64_t* words, int64_t partial_words) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < partial_words;
        i += (int64_t)gridDim.x * blockDim.x)
     partial[i] = 0ull;
+}
+
+// The default workspace of (device, stream) if it exists or can be created
+// now (not under graph capture), else null; sets no error.
+rd_workspace* default_workspace_quiet(int device, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto key = std::make_pair(device, s);
+  auto it = g_default_ws.find(key);
+  if (it != g_default_ws.end()) return it->second;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  rd_workspace* w = nullptr;
+  if (create_workspace_quiet(&w, device) != RD_OK) return nullptr;
+  g_default_ws[key] = w;
+  return w;
 }
 
 // Resolve the caller's workspace or the default one for (device, stream).
@@ -810,14 +835,19 @@ rd_status rd_rowreduce_bwd(const void* x, const void* g, const void* saved, int6
   const rd::Launch l = row_launch(RD_KIND_ROWWISE_BWD, op, rows, cols);
   hipError_t e;
   if (op == RD_PROD && dev >= 0 && dev < kSideMaxDevices) {
+    // The exclusive-product kernel's tile counter: the scan's counter words of
+    // the stream's default workspace (zero between launches; the same stream
+    // orders every user of them).
+    rd_workspace* w = default_workspace_quiet(dev, (hipStream_t)stream);
+    unsigned* dyn_ctl = w ? w->scratch.scan_ctl : nullptr;
     SideDevice& ss = g_side[dev];
     std::lock_guard<std::mutex> lock(ss.mu);
     side_setup(ss);
     e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in, info.cus, l,
-                          (hipStream_t)stream, ss.path);
+                          (hipStream_t)stream, ss.path, dyn_ctl);
   } else {
     e = rd::rowreduce_bwd((const float*)x, (const float*)g, saved, rows, cols, op, (float*)grad_in, info.cus, l,
-                          (hipStream_t)stream, rd::SidePath{});
+                          (hipStream_t)stream, rd::SidePath{}, nullptr);
   }
   return e == hipSuccess ? RD_OK : hip_fail(e, "rd_rowreduce_bwd launch");
 }

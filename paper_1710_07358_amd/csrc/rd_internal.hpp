@@ -135,9 +135,11 @@ struct SidePath {
   hipStream_t stream = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
 };
+// dyn_ctl: two words (zero between launches, left zero) for the product's
+// tile counter, or null (then the strided kernel runs).
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows,
                          int64_t cols, rd_op op, float* grad, int cus, const Launch& l, hipStream_t s,
-                         const SidePath& side);
+                         const SidePath& side, unsigned* dyn_ctl);
 size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols);
 
 // The paper's two designs (sum of int32 / float32), for comparison:

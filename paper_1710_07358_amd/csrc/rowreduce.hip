@@ -395,6 +395,25 @@ __global__ __launch_bounds__(kRowBlock) void row_fwd_kernel(const float* __restr
 
 // ------------------------------------------------------------------ backward
 
+// Division of a work-group index by a launch constant d (1 <= d < 2^31),
+// exact for every 32-bit dividend, with one multiply-high, a subtraction and
+// shifts (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994: the round-down method with an added correction).
+// The host computes m, s1 and s2 once per launch.
+struct DivMagic {
+  uint32_t m, s1, s2;
+};
+inline DivMagic div_magic(uint32_t d) {
+  uint32_t l = 0;  // ceil(log2 d)
+  while ((1ull << l) < d) ++l;
+  return DivMagic{(uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l < 1 ? l : 1u, l > 0 ? l - 1 : 0u};
+}
+__device__ __forceinline__ uint32_t div_by(uint32_t n, DivMagic q) {
+  const uint32_t t = __umulhi(n, q.m);
+  return (t + ((n - t) >> q.s1)) >> q.s2;
+}
+
+
 // Product gradient over a flat grid of (row, chunk) tiles, one work-group of
 // kProdBlock work-items per tile.  Work-item t holds kProdStripes stripes of
 // 4 consecutive columns: stripe s covers columns s * kProdBlock * 4 + 4t ..
@@ -413,8 +432,58 @@ constexpr int kProdWaves = kProdBlock / 64;
 constexpr int kProdStripes = (int)(kChunk / (kProdBlock * 4));
 static_assert(kProdStripes * kProdWaves == 64, "one wavefront scans the chunk's pieces");
 
-// At most 64 VGPRs, so two work-groups fit on a CU (8 wavefronts per SIMD);
-// beside the fill on the side stream it runs one work-group per CU.
+// x of tile (r, k): stripes of 4 consecutive columns, ragged columns as 1.0.
+template <bool AL, bool NT>
+__device__ __forceinline__ void load_prod_tile(const float* __restrict__ x, int64_t r, int64_t k, int64_t cols,
+                                               int t, float (&v)[kProdStripes][4]) {
+  const int64_t c0 = k * kChunk;
+  const bool full = c0 + kChunk <= cols;
+#pragma unroll
+  for (int s = 0; s < kProdStripes; ++s)
+    load_stripe<AL, NT>(x + r * cols, c0 + ((int64_t)s * kProdBlock + t) * 4, cols, full, 1.0f, v[s]);
+}
+
+// Gradient of tile (r, k) of a zero-free row from its x (one barrier:
+// every wavefront scans the 64 piece products, which go through `piece`,
+// 64 floats of LDS the caller does not reuse before the next barrier).
+template <bool AL, bool NT>
+__device__ __forceinline__ void prod_tile(const float (&v)[kProdStripes][4], int64_t r, int64_t k, int64_t cols,
+                                          int64_t nch, const float* __restrict__ g, const double* __restrict__ pre,
+                                          const double* __restrict__ suf, float* __restrict__ grad, float* piece,
+                                          int t, int lane, int wave) {
+  const int64_t c0 = k * kChunk;
+  const bool full = c0 + kChunk <= cols;
+  // the rest of the row (chunks before and after), times g, in float64
+  const float K = (float)((double)g[r] * pre[r * nch + k] * suf[r * nch + k]);
+  float before[kProdStripes], after[kProdStripes];
+#pragma unroll
+  for (int s = 0; s < kProdStripes; ++s) {
+    const float m = (v[s][0] * v[s][1]) * (v[s][2] * v[s][3]);  // this work-item's 4 columns
+    float all;
+    wave_excl_products(m, &before[s], &after[s], &all);
+    if (lane == 0) piece[s * kProdWaves + wave] = all;
+  }
+  __syncthreads();
+  float pb, pa, pall;
+  wave_excl_products(piece[lane], &pb, &pa, &pall);
+  float* __restrict__ grow = grad + r * cols;
+#pragma unroll
+  for (int s = 0; s < kProdStripes; ++s) {
+    const int pc = s * kProdWaves + wave;  // wavefront-uniform
+    const float left = (K * readlane(pb, pc)) * before[s];
+    const float right = after[s] * readlane(pa, pc);
+    const float p01 = v[s][0] * v[s][1], p23 = v[s][2] * v[s][3];
+    float o[4];
+    o[0] = left * (v[s][1] * p23) * right;
+    o[1] = left * (v[s][0] * p23) * right;
+    o[2] = left * (p01 * v[s][3]) * right;
+    o[3] = left * (p01 * v[s][2]) * right;
+    const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
+    if (col < cols) store_stripe<AL, NT>(grow, col, cols, full, o);
+  }
+}
+
+// At most 64 VGPRs, so two work-groups fit on a CU (8 wavefronts per SIMD).
 // Persistent: work-group w takes the tiles w, w + G, w + 2G, ... (G groups).
 // Every wavefront reads the row headers (and g) of 64 of those tiles at once,
 // one per lane, so tiles of rows with zeros -- written by
@@ -422,7 +491,8 @@ static_assert(kProdStripes * kProdWaves == 64, "one wavefront scans the chunk's 
 // zero-free rows the next tile's x is loaded before the current tile is
 // processed (the last tile of a batch of 64 is peeled, so every prefetch is
 // unconditional), and a tile needs one barrier: every wavefront scans the 64
-// piece products itself.
+// piece products itself.  Used where the tile-counter kernel below does not
+// apply.
 template <bool AL, bool NT>
 __global__ __launch_bounds__(kProdBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ g, const void* __restrict__ saved,
@@ -441,44 +511,13 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
     return r;
   };
   const auto load_tile = [&](int64_t b, float (&v)[kProdStripes][4]) {
-    const int64_t r = row_of(b), c0 = (b - r * nch) * kChunk;
-    const bool full = c0 + kChunk <= cols;
-#pragma unroll
-    for (int s = 0; s < kProdStripes; ++s)
-      load_stripe<AL, NT>(x + r * cols, c0 + ((int64_t)s * kProdBlock + t) * 4, cols, full, 1.0f, v[s]);
+    const int64_t r = row_of(b);
+    load_prod_tile<AL, NT>(x, r, b - r * nch, cols, t, v);
   };
   int parity = 0;
   const auto process = [&](int64_t b, const float (&v)[kProdStripes][4]) {
-    const int64_t r = row_of(b), k = b - r * nch, c0 = k * kChunk;
-    const bool full = c0 + kChunk <= cols;
-    // the rest of the row (chunks before and after), times g, in float64
-    const float K = (float)((double)g[r] * pre[r * nch + k] * suf[r * nch + k]);
-    float before[kProdStripes], after[kProdStripes];
-#pragma unroll
-    for (int s = 0; s < kProdStripes; ++s) {
-      const float m = (v[s][0] * v[s][1]) * (v[s][2] * v[s][3]);  // this work-item's 4 columns
-      float all;
-      wave_excl_products(m, &before[s], &after[s], &all);
-      if (lane == 0) lds_piece[parity][s * kProdWaves + wave] = all;
-    }
-    __syncthreads();
-    float pb, pa, pall;
-    wave_excl_products(lds_piece[parity][lane], &pb, &pa, &pall);
-    float* __restrict__ grow = grad + r * cols;
-#pragma unroll
-    for (int s = 0; s < kProdStripes; ++s) {
-      const int piece = s * kProdWaves + wave;  // wavefront-uniform
-      const float left = (K * readlane(pb, piece)) * before[s];
-      const float right = after[s] * readlane(pa, piece);
-      const float p01 = v[s][0] * v[s][1], p23 = v[s][2] * v[s][3];
-      float o[4];
-      o[0] = left * (v[s][1] * p23) * right;
-      o[1] = left * (v[s][0] * p23) * right;
-      o[2] = left * (p01 * v[s][3]) * right;
-      o[3] = left * (p01 * v[s][2]) * right;
-      const int64_t col = c0 + ((int64_t)s * kProdBlock + t) * 4;
-      if (col < cols) store_stripe<AL, NT>(grow, col, cols, full, o);
-    }
+    const int64_t r = row_of(b);
+    prod_tile<AL, NT>(v, r, b - r * nch, cols, nch, g, pre, suf, grad, lds_piece[parity], t, lane, wave);
     parity ^= 1;  // the next tile writes the other array: no second barrier
   };
   for (int64_t base = blockIdx.x; base < total; base += 64 * G) {
@@ -510,22 +549,77 @@ void row_prod_bwd_kernel(const float* __restrict__ x, const float* __restrict__ 
   }
 }
 
-// Division of a work-group index by a launch constant d (1 <= d < 2^31),
-// exact for every 32-bit dividend, with one multiply-high, a subtraction and
-// shifts (Granlund and Montgomery, "Division by invariant integers using
-// multiplication", 1994: the round-down method with an added correction).
-// The host computes m, s1 and s2 once per launch.
-struct DivMagic {
-  uint32_t m, s1, s2;
-};
-inline DivMagic div_magic(uint32_t d) {
-  uint32_t l = 0;  // ceil(log2 d)
-  while ((1ull << l) < d) ++l;
-  return DivMagic{(uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l < 1 ? l : 1u, l > 0 ? l - 1 : 0u};
-}
-__device__ __forceinline__ uint32_t div_by(uint32_t n, DivMagic q) {
-  const uint32_t t = __umulhi(n, q.m);
-  return (t + ((n - t) >> q.s1)) >> q.s2;
+// The same gradient with tiles handed out in order by a counter, one per
+// grab, to one work-group per CU: the tiles in flight are then neighbours in
+// memory, as in a flat launch, while a fixed stride lets work-groups drift
+// apart.  Measured on MI355X for 8 GiB of plain read+write (one 1024-wide
+// work-group per CU, 4 loads and 4 stores per work-item per tile): strided
+// 1.53 ms, counter 1.29 ms, counter in batches of 2 / 4 / 16 tiles per grab
+// 1.38 / 1.46 / 1.60 ms, a flat launch 1.31 ms.
+//   The zero-free rows come first, as a bitmap in LDS built from the row
+// headers (rows <= kDynRows); a launch in which every row holds a zero
+// leaves at once, and a tile of a row with zeros costs one grab.  Each
+// grab is issued one tile ahead.  ctl[1] is the counter and ctl[2] counts
+// the work-groups that finished: the last one re-arms both to zero.
+constexpr int64_t kDynRows = 65536;
+
+template <bool AL, bool NT>
+__global__ __launch_bounds__(kProdBlock)
+void row_prod_bwd_dyn_kernel(const float* __restrict__ x, const float* __restrict__ g,
+                             const void* __restrict__ saved, int64_t rows, int64_t cols, int64_t nch, DivMagic dm,
+                             float* __restrict__ grad, unsigned* __restrict__ ctl) {
+  __shared__ float lds_piece[2][64];
+  __shared__ uint32_t lds_zf[kDynRows / 32];  // bit r % 32 of word r / 32: row r has no zero
+  __shared__ unsigned lds_tile[2];
+  __shared__ int lds_any;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const ProdHeader* __restrict__ hdr = (const ProdHeader*)saved;
+  if (t == 0) lds_any = 0;
+  __syncthreads();
+  bool any = false;
+  for (int64_t base = (int64_t)wave * 64; base < rows; base += (int64_t)kProdWaves * 64) {
+    const int64_t r = base + lane;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(r < rows && hdr[r].zeros == 0);
+    if (lane == 0) {  // rows base .. base + 63: words base / 32 and base / 32 + 1
+      lds_zf[base >> 5] = (uint32_t)m;
+      lds_zf[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+    any = any || m != 0ull;
+  }
+  if (any && lane == 0) lds_any = 1;
+  __syncthreads();
+  if (lds_any != 0) {
+    const double* __restrict__ pre = prod_prefix((void*)saved, rows);
+    const double* __restrict__ suf = prod_suffix((void*)saved, rows, nch);
+    const unsigned total = (unsigned)(rows * nch);  // < 2^31 (the host checks)
+    const auto grab = [&]() { return __hip_atomic_fetch_add(ctl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    if (t == 0) lds_tile[0] = grab();
+    __syncthreads();
+    unsigned b = lds_tile[0];
+    int par = 1, parity = 0;
+    while (b < total) {
+      if (t == 0) lds_tile[par] = grab();  // the next tile, in flight during this one
+      const uint32_t r = div_by(b, dm);
+      if ((lds_zf[r >> 5] >> (r & 31)) & 1u) {  // the same in every work-item
+        const int64_t k = (int64_t)(b - r * (uint32_t)nch);
+        float v[kProdStripes][4];
+        load_prod_tile<AL, NT>(x, r, k, cols, t, v);
+        prod_tile<AL, NT>(v, r, k, cols, nch, g, pre, suf, grad, lds_piece[parity], t, lane, wave);
+        parity ^= 1;
+      }
+      __syncthreads();  // lds_tile[par] written
+      b = lds_tile[par];
+      par ^= 1;
+    }
+  }
+  if (t == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(ctl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {  // every grab of this launch is done
+      __hip_atomic_store(ctl + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctl + 2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // Write-only gradients (sum; min/max; product rows with zeros), one tile of
@@ -682,19 +776,37 @@ hipError_t prod_bwd_launch(const float* x, const float* g, const void* saved, in
 // the other streams); every row with zeros 0.60 -> 0.62 ms (the fork and
 // the join).  The caller's stream waits for the side stream before anything
 // after the call.
+// The exclusive-product kernel on stream s: the tile-counter kernel (one
+// work-group per CU) where its counter words are given and its limits hold,
+// else the strided one.
+template <bool AL>
+hipError_t dense_launch(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
+                        float* grad, int cus, int strided_groups, bool nt, unsigned* dyn_ctl, hipStream_t s) {
+  const int64_t nch = chunks_of(cols);
+  if (dyn_ctl != nullptr && rows <= kDynRows && rows * nch < ((int64_t)1 << 31)) {
+    const DivMagic dm = div_magic((uint32_t)nch);
+    if (nt) hipLaunchKernelGGL((row_prod_bwd_dyn_kernel<AL, true>), dim3((unsigned)cus), dim3(kProdBlock), 0, s, x,
+                               g, saved, rows, cols, nch, dm, grad, dyn_ctl);
+    else hipLaunchKernelGGL((row_prod_bwd_dyn_kernel<AL, false>), dim3((unsigned)cus), dim3(kProdBlock), 0, s, x,
+                            g, saved, rows, cols, nch, dm, grad, dyn_ctl);
+    return hipGetLastError();
+  }
+  return prod_bwd_launch<AL>(x, g, saved, rows, cols, grad, strided_groups, nt, s);
+}
+
 template <bool AL>
 hipError_t prod_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, float* grad,
-                    int cus, bool nt, hipStream_t s, const SidePath& side) {
+                    int cus, bool nt, hipStream_t s, const SidePath& side, unsigned* dyn_ctl) {
   if (side.stream == nullptr) {
     const hipError_t e = fill_launch<Op::Prod, AL>(g, saved, rows, cols, grad, nt, s);
     if (e != hipSuccess) return e;
-    return prod_bwd_launch<AL>(x, g, saved, rows, cols, grad, cus * 2, nt, s);
+    return dense_launch<AL>(x, g, saved, rows, cols, grad, cus, cus * 2, nt, dyn_ctl, s);
   }
   hipError_t e = hipEventRecord(side.fork, s);
   if (e != hipSuccess) return e;
   e = hipStreamWaitEvent(side.stream, side.fork, 0);
   if (e != hipSuccess) return e;
-  const hipError_t e_dense = prod_bwd_launch<AL>(x, g, saved, rows, cols, grad, cus, nt, s);
+  const hipError_t e_dense = dense_launch<AL>(x, g, saved, rows, cols, grad, cus, cus, nt, dyn_ctl, s);
   const hipError_t e_fill = fill_launch<Op::Prod, AL>(g, saved, rows, cols, grad, nt, side.stream);
   e = hipEventRecord(side.join, side.stream);  // joined whatever the launches returned
   if (e == hipSuccess) e = hipStreamWaitEvent(s, side.join, 0);
@@ -705,10 +817,10 @@ hipError_t prod_bwd(const float* x, const float* g, const void* saved, int64_t r
 
 template <Op O>
 hipError_t bwd_op(bool al, const float* x, const float* g, const void* saved, int64_t rows, int64_t cols,
-                  float* grad, int cus, bool nt, hipStream_t s, const SidePath& side) {
+                  float* grad, int cus, bool nt, hipStream_t s, const SidePath& side, unsigned* dyn_ctl) {
   if constexpr (O == Op::Prod) {
-    return al ? prod_bwd<true>(x, g, saved, rows, cols, grad, cus, nt, s, side)
-              : prod_bwd<false>(x, g, saved, rows, cols, grad, cus, nt, s, side);
+    return al ? prod_bwd<true>(x, g, saved, rows, cols, grad, cus, nt, s, side, dyn_ctl)
+              : prod_bwd<false>(x, g, saved, rows, cols, grad, cus, nt, s, side, dyn_ctl);
   } else {
     return al ? fill_launch<O, true>(g, saved, rows, cols, grad, nt, s)
               : fill_launch<O, false>(g, saved, rows, cols, grad, nt, s);
@@ -730,13 +842,14 @@ hipError_t rowreduce_fwd(const float* x, int64_t rows, int64_t cols, rd_op op, f
 }
 
 hipError_t rowreduce_bwd(const float* x, const float* g, const void* saved, int64_t rows, int64_t cols, rd_op op,
-                         float* grad, int cus, const Launch& l, hipStream_t s, const SidePath& side) {
+                         float* grad, int cus, const Launch& l, hipStream_t s, const SidePath& side,
+                         unsigned* dyn_ctl) {
   const bool al = (cols % 4 == 0) && ((uintptr_t)grad % 16 == 0) && (op != RD_PROD || (uintptr_t)x % 16 == 0);
   switch (op) {
-    case RD_SUM: return bwd_op<Op::Sum>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side);
-    case RD_MAX: return bwd_op<Op::Max>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side);
-    case RD_MIN: return bwd_op<Op::Min>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side);
-    case RD_PROD: return bwd_op<Op::Prod>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side);
+    case RD_SUM: return bwd_op<Op::Sum>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side, dyn_ctl);
+    case RD_MAX: return bwd_op<Op::Max>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side, dyn_ctl);
+    case RD_MIN: return bwd_op<Op::Min>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side, dyn_ctl);
+    case RD_PROD: return bwd_op<Op::Prod>(al, x, g, saved, rows, cols, grad, cus, l.nontemporal, s, side, dyn_ctl);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,7 +30,7 @@ hipError_t rowreduce_fwd(const float*, int64_t, int64_t, rd_op, float*, void*, i
   return hipErrorInvalidValue;
 }
 hipError_t rowreduce_bwd(const float*, const float*, const void*, int64_t, int64_t, rd_op, float*, int,
-                         const Launch&, hipStream_t, const SidePath&) {
+                         const Launch&, hipStream_t, const SidePath&, unsigned*) {
   return hipErrorInvalidValue;
 }
 size_t rowreduce_saved_bytes(rd_op op, int64_t rows, int64_t cols) {
